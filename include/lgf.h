@@ -1,0 +1,161 @@
+/*
+ * lgf.h -- Fourier-accelerated steepest-descent Landau gauge fixing of 4D
+ * SU(3) lattice gauge fields on an AMD MI355X (gfx950), C ABI.
+ *
+ * The method (Cardoso, Silva, Oliveira, Bicudo, "Landau gauge fixing on the
+ * lattice using GPU's", arXiv:1301.3460):
+ *
+ *   Landau gauge maximises, on each gauge orbit, the functional of the
+ *   paper's display equation
+ *       F_U[g] = 1/(Nd Nc V) sum_x sum_mu Re Tr[ g(x) U_mu(x) g(x+mu)^dagger ],
+ *   Nd = 4, Nc = 3, V = Lx Ly Lz Lt.  It is maximised by steepest descent with
+ *   Fourier acceleration (the text following the display equation), with the
+ *   step parameter alpha = 0.08 and the stopping criterion theta < 1e-15 of
+ *   the paper's 32^4 comparison runs.
+ *
+ * The paper does not print the iteration formulae; this library uses the
+ * reading of the cited method documented with the sources:
+ *   Delta(x) = A - Tr(A)/3,  A = X - X^dagger,  X = sum_mu [U_mu(x-mu) - U_mu(x)]
+ *   theta    = 1/(Nc V) sum_x Tr[Delta(x) Delta(x)^dagger]
+ *   g(x)     = reunit(1 + (alpha/2) IFFT[ p2max/p2(p) * FFT[Delta] ](x)),
+ *              p2(p) = sum_mu 4 sin^2(pi p_mu/L_mu), zero mode dropped,
+ *              reunit = Gram-Schmidt of rows 0,1 and row 2 = conj(row0 x row1)
+ *   U_mu(x) <- g(x) U_mu(x) g(x+mu)^dagger  (all links at once)
+ *
+ * Conventions shared by every entry point
+ *   Lattice      L[4] = {Lx, Ly, Lz, Lt}; each extent is one of
+ *                2 3 4 6 8 12 16 24 32 48 64 96 128.  Periodic boundaries.
+ *                Site index s = x + Lx*(y + Ly*(z + Lz*t)).
+ *   Links U      DEVICE pointer to complex128 data (interleaved re, im)
+ *                laid out [4][Lt][Lz][Ly][Lx][3][3] (mu = x, y, z, t), i.e. a
+ *                contiguous torch.complex128 tensor of shape (4,Lt,Lz,Ly,Lx,3,3).
+ *                Only rows 0 and 1 of every link are read: the library stores
+ *                links as 12 reals and rebuilds row 2 = conj(row0 x row1),
+ *                which is exact for SU(3).  Links written back are full 3x3.
+ *   Site fields  DEVICE pointers; g: complex128 [Lt][Lz][Ly][Lx][3][3];
+ *                omega, dF/domega: float64 [Lt][Lz][Ly][Lx][8];
+ *                eps, dtheta/deps: float64 [4][Lt][Lz][Ly][Lx][8].
+ *                Generators T^a = lambda_a/2 (Gell-Mann matrices lambda_1..8).
+ *   Ownership    The caller owns every pointer it passes.  The context owns
+ *                its device scratch (working links, Fourier fields, partial
+ *                sums), allocated in lgf_create and freed in lgf_destroy.
+ *   Ordering     All device work is enqueued on the context's stream.  Calls
+ *                that return host scalars synchronise that stream first.
+ *   Errors       Every call returns an lgf_status value; no C++ exception
+ *                crosses the ABI.  lgf_last_error() gives a message.  On
+ *                LGF_ERR_ARG no device memory is touched.  Solver statuses
+ *                LGF_NOT_CONVERGED / LGF_ERR_NONFINITE / LGF_DIVERGING still
+ *                fill the result and write back the last completed iterate.
+ *   Threads      A context may be used by one host thread at a time.
+ */
+#ifndef LGF_H
+#define LGF_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lgf_ctx lgf_ctx;
+
+typedef enum {
+    LGF_OK = 0,
+    LGF_ERR_ARG = 1,          /* invalid argument (pointer, extent, alpha, tol) */
+    LGF_ERR_DEVICE = 2,       /* a HIP call failed */
+    LGF_ERR_OOM = 3,          /* device allocation failed */
+    LGF_NOT_CONVERGED = 4,    /* max_iter updates applied, theta >= tol */
+    LGF_ERR_NONFINITE = 5,    /* theta became NaN or Inf */
+    LGF_DIVERGING = 6         /* theta rose for 8 consecutive iterations */
+} lgf_status;
+
+typedef enum {
+    LGF_FP64 = 0,   /* every sweep in double precision */
+    LGF_MIXED = 1   /* FP32 sweeps until theta < theta_switch, then FP64 */
+} lgf_precision;
+
+typedef struct {
+    int iterations;       /* gauge updates applied by the call (all phases) */
+    int fp32_iterations;  /* of which in the FP32 phase (LGF_MIXED only) */
+    int status;           /* lgf_status of the solve */
+    double F;             /* F_U[1] of the returned links */
+    double theta;         /* theta of the returned links */
+    double seconds;       /* wall time of the call, device work included */
+} lgf_result;
+
+/* Create a context for lattice L (see conventions) and precision mode.
+ * stream: a hipStream_t to enqueue on (NULL: the null stream).  The current
+ * HIP device at creation is the context's device.  *out receives the context. */
+int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream);
+
+/* Free the context's device scratch; NULL is ignored. */
+void lgf_destroy(lgf_ctx *ctx);
+
+/* Threshold at which LGF_MIXED hands over from FP32 to FP64 (default 1e-8). */
+int lgf_set_theta_switch(lgf_ctx *ctx, double theta_switch);
+
+/* Exactly n_iter Fourier-accelerated updates of the links U (in place), with
+ * no stopping test (n_iter >= 0).  res (may be NULL) gets F and theta of the
+ * returned links.  LGF_FP64 only semantics: a LGF_MIXED context runs the
+ * sweeps in FP32 and accumulates the transformation, applying it to U in
+ * FP64 at the end. */
+int lgf_iterate(lgf_ctx *ctx, double *U, double alpha, int n_iter, lgf_result *res);
+
+/* Gauge fixing: updates U in place until theta < theta_tol (tested before
+ * each update, so an already-fixed input takes 0 updates) or max_iter
+ * updates.  alpha > 0, theta_tol > 0, max_iter >= 0. */
+int lgf_fix(lgf_ctx *ctx, double *U, double alpha, double theta_tol, int max_iter,
+            lgf_result *res);
+
+/* F_U[g] of the display equation (g == NULL: identity) into *F (host). */
+int lgf_functional(lgf_ctx *ctx, const double *U, const double *g, double *F);
+
+/* theta of the links U into *theta (host). */
+int lgf_theta(lgf_ctx *ctx, const double *U, double *theta);
+
+/* Average plaquette 1/(6 Nc V) sum_x sum_{mu<nu} Re Tr U_mu(x) U_nu(x+mu)
+ * U_mu(x+nu)^dagger U_nu(x)^dagger into *P (host): a gauge-invariant check. */
+int lgf_plaquette(lgf_ctx *ctx, const double *U, double *P);
+
+/* Per-step entry points, for step-by-step checking of the sweep.
+ * lgf_divergence: Delta(x) of U as complex128 [Lt][Lz][Ly][Lx][3][3].
+ * lgf_fourier_accelerate: LD = IFFT[p2max/p2 * FFT[D]] of an anti-hermitian
+ *   traceless site field D (same layout, only its independent entries read).
+ * lgf_fft4d: unnormalised 4D DFT, in place, of 4 complex128 fields laid out
+ *   [4][Lt][Lz][Ly][Lx]; sign = -1 forward exp(-2 pi i n.x/L), +1 inverse. */
+int lgf_divergence(lgf_ctx *ctx, const double *U, double *Delta);
+int lgf_fourier_accelerate(lgf_ctx *ctx, const double *D, double *LD);
+int lgf_fft4d(lgf_ctx *ctx, double *fields, int sign);
+
+/* Differentiation (FP64).  g(x) = exp(i omega^a(x) T^a), exactly.
+ * lgf_functional_omega: *F = F_U[g].
+ * lgf_functional_omega_grad: *F and dF/domega^a(x) into dF (device). */
+int lgf_functional_omega(lgf_ctx *ctx, const double *U, const double *omega, double *F);
+int lgf_functional_omega_grad(lgf_ctx *ctx, const double *U, const double *omega,
+                              double *F, double *dF);
+
+/* theta of the links U'_mu(x) = exp(i eps^a_mu(x) T^a) U_mu(x) (eps == NULL:
+ * zero) and its derivative dtheta/deps^a_mu(x) (device, may be NULL). */
+int lgf_theta_grad(lgf_ctx *ctx, const double *U, const double *eps, double *theta,
+                   double *dtheta);
+
+/* Per-iteration history of the last lgf_fix/lgf_iterate: F_n and theta_n for
+ * n = 0..iterations (FP32 phase first in LGF_MIXED).  Copies at most cap
+ * entries into host arrays; *count receives the number of entries. */
+int lgf_history(lgf_ctx *ctx, double *F, double *theta, int cap, int *count);
+
+/* Per-kernel timing of n_iter sweeps (n_iter >= 1) of the context's precision
+ * (LGF_MIXED: the FP32 sweep with transformation accumulation), run on the
+ * context's working copy of U (U itself is not modified).  HIP events are
+ * recorded between the launches of every sweep, all sweeps are enqueued
+ * before one synchronisation, and kernel_ms[k] receives the mean duration in
+ * milliseconds of: 0 (x,y) forward FFT, 1 (z,t) FFT + scaling + inverse,
+ * 2 (x,y) inverse FFT, 3 update + next divergence, 4 finalize. */
+int lgf_profile(lgf_ctx *ctx, const double *U, double alpha, int n_iter, double *kernel_ms);
+
+/* Message for the last failure on ctx (ctx == NULL: last failure of
+ * lgf_create on this thread).  Never NULL. */
+const char *lgf_last_error(const lgf_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LGF_H */

@@ -1,0 +1,721 @@
+// Host side of the C ABI declared in include/lgf.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/lgf.h"
+#include "fft.hpp"
+#include "kernels.hpp"
+
+using namespace lgf;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr int HIST_CAP = 1 << 16;
+constexpr size_t ZT_LDS_BUDGET = 80 * 1024;  // bytes of LDS per (z,t) tile
+
+struct Timer {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double seconds() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+}  // namespace
+
+struct lgf_ctx {
+    geom g{};
+    int precision = LGF_FP64;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    double p2max = 0;
+    double theta_switch = 1e-8;
+
+    // working links, SoA-12: FP64 double buffer; the FP32 pair aliases L64[1]
+    double2 *L64[2] = {nullptr, nullptr};
+    float2 *L32[2] = {nullptr, nullptr};
+    float2 *G32 = nullptr;
+    // Fourier fields (4 complex per site), FP64 size; FP32 views alias them
+    double2 *D64[2] = {nullptr, nullptr};
+    // tables
+    double2 *tw64 = nullptr;
+    float2 *tw32 = nullptr;
+    double *pt64 = nullptr;
+    float *pt32 = nullptr;
+    int W64 = 1, W32 = 1;
+    // reductions and control
+    double *partials = nullptr;
+    int nparts = 0;
+    dev_status *status = nullptr;
+    dev_status *status_host = nullptr;  // pinned
+    double *reduce_out = nullptr;       // device [2]
+    double *reduce_host = nullptr;      // pinned [2]
+    double *histF = nullptr, *histT = nullptr;
+    int hist_len = 0;
+    // differentiation scratch (allocated on first use)
+    double *gaos = nullptr;   // V*9 complex or 4V*9 complex (link exponentials)
+    double2 *Lrot = nullptr;  // SoA-12 FP64 links
+    std::string err;
+};
+
+namespace {
+
+int fail(lgf_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(ctx, LGF_ERR_DEVICE,                                                  \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+    } while (0)
+
+double normF(const lgf_ctx *c) { return 1.0 / (4.0 * 3.0 * (double)c->g.V); }
+double normT(const lgf_ctx *c) { return 1.0 / (3.0 * (double)c->g.V); }
+
+// tw[j] = exp(-2 pi i j / TW_M), long double
+template <class V2> std::vector<V2> make_twiddles() {
+    std::vector<V2> t(TW_M);
+    const long double twopi = 6.283185307179586476925286766559005768L;
+    for (int j = 0; j < TW_M; ++j) {
+        long double a = twopi * (long double)j / (long double)TW_M;
+        t[j].x = (decltype(t[j].x))cosl(a);
+        t[j].y = (decltype(t[j].y))(-sinl(a));
+    }
+    return t;
+}
+
+// Per-axis 4 sin^2(pi k / L) indexed by transform position (see fft_freq_of_pos).
+std::vector<long double> make_p2_tables(const geom &g, long double &p2max) {
+    const int L[4] = {g.Lx, g.Ly, g.Lz, g.Lt};
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<long double> t;
+    p2max = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        long double mx = 0;
+        for (int p = 0; p < L[mu]; ++p) {
+            const int k = fft_freq_of_pos(L[mu], p);
+            const long double s = sinl(pi * (long double)k / (long double)L[mu]);
+            t.push_back(4.0L * s * s);
+            if (4.0L * s * s > mx) mx = 4.0L * s * s;
+        }
+        p2max += mx;
+    }
+    return t;
+}
+
+template <class T> int pick_W(const geom &g) {
+    const long Lxy = (long)g.Lx * g.Ly;
+    int W = 16;
+    while (W > 1 && ((long)W > Lxy || fft_zt_lds_bytes<T>(g, W) > ZT_LDS_BUDGET)) W >>= 1;
+    return W;
+}
+
+bool shape_ok(const int L[4]) {
+    for (int mu = 0; mu < 4; ++mu)
+        if (!fft_supported(L[mu])) return false;
+    return true;
+}
+
+// ------------------------------------------------------------------ sweep
+
+template <class T> struct prec;
+template <> struct prec<double> {
+    static void *links(lgf_ctx *c, int i) { return c->L64[i]; }
+    static void *field(lgf_ctx *c, int i) { return c->D64[i]; }
+    static const void *tw(lgf_ctx *c) { return c->tw64; }
+    static const double *pt(lgf_ctx *c) { return c->pt64; }
+    static int W(lgf_ctx *c) { return c->W64; }
+};
+template <> struct prec<float> {
+    static void *links(lgf_ctx *c, int i) { return c->L32[i]; }
+    static void *field(lgf_ctx *c, int i) { return c->D64[i]; }
+    static const void *tw(lgf_ctx *c) { return c->tw32; }
+    static const float *pt(lgf_ctx *c) { return c->pt32; }
+    static int W(lgf_ctx *c) { return c->W32; }
+};
+
+// One Fourier-accelerated sweep from links/field buffer `cur` into `cur^1`.
+template <class T> hipError_t enqueue_sweep(lgf_ctx *c, int cur, T half_alpha, bool accG) {
+    using P = prec<T>;
+    hipError_t e;
+    void *D = P::field(c, cur);
+    if ((e = launch_fft_xy<T>(c->g, D, -1, P::tw(c), c->status, c->stream)) != hipSuccess) return e;
+    if ((e = launch_fft_zt<T>(c->g, D, 0, P::tw(c), P::pt(c), (T)(c->p2max / (double)c->g.V),
+                              P::W(c), c->status, c->stream)) != hipSuccess)
+        return e;
+    if ((e = launch_fft_xy<T>(c->g, D, +1, P::tw(c), c->status, c->stream)) != hipSuccess) return e;
+    return launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
+                            accG ? c->G32 : nullptr, half_alpha, c->partials, c->status, c->stream);
+}
+
+int read_status(lgf_ctx *c, dev_status &out) {
+    HIPCHK(c, hipMemcpyAsync(c->status_host, c->status, sizeof(dev_status), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    out = *c->status_host;
+    return LGF_OK;
+}
+
+// Runs one precision phase on the working links in buffer 0.  On return the
+// current links are in buffer (n % 2) and `st` holds the final state.
+template <class T>
+int run_phase(lgf_ctx *c, double alpha, double tol, int max_iter, bool accG, int hist_base,
+              dev_status &st) {
+    using P = prec<T>;
+    HIPCHK(c, launch_status_reset(c->status, hist_base, c->stream));
+    HIPCHK(c, launch_div_reduce<T>(c->g, P::links(c, 0), P::field(c, 0), c->partials, c->status,
+                                   c->stream));
+    HIPCHK(c, launch_finalize(c->partials, c->nparts, c->status, normF(c), normT(c), tol, max_iter,
+                              0, c->histF, c->histT, HIST_CAP, c->stream));
+    int rc = read_status(c, st);
+    if (rc) return rc;
+    const T half_alpha = (T)(0.5 * alpha);
+    int enq = 0;  // sweeps enqueued so far
+    double th_prev = st.theta;
+    int n_prev = st.n;
+    while (!st.done) {
+        // predict the sweeps still needed from the observed contraction rate
+        int k = 4;
+        if (st.n > n_prev && st.theta > 0 && th_prev > 0) {
+            double rate = std::pow(st.theta / th_prev, 1.0 / (double)(st.n - n_prev));
+            rate = std::min(std::max(rate, 1e-3), 0.95);
+            const double need = std::log(tol / st.theta) / std::log(rate);
+            k = (int)std::ceil(std::max(need, 1.0));
+        }
+        k = std::max(1, std::min(k, 64));
+        k = std::min(k, max_iter - enq);
+        if (k <= 0) k = 1;  // the finalize of the last sweep sets done
+        th_prev = st.theta;
+        n_prev = st.n;
+        for (int i = 0; i < k; ++i) {
+            const int cur = (enq + i) & 1;
+            HIPCHK(c, enqueue_sweep<T>(c, cur, half_alpha, accG));
+            HIPCHK(c, launch_finalize(c->partials, c->nparts, c->status, normF(c), normT(c), tol,
+                                      max_iter, 1, c->histF, c->histT, HIST_CAP, c->stream));
+        }
+        enq += k;
+        rc = read_status(c, st);
+        if (rc) return rc;
+    }
+    return LGF_OK;
+}
+
+int status_to_code(int code) {
+    switch (code) {
+    case ST_CONVERGED: return LGF_OK;
+    case ST_MAXITER: return LGF_NOT_CONVERGED;
+    case ST_NONFINITE: return LGF_ERR_NONFINITE;
+    case ST_DIVERGING: return LGF_DIVERGING;
+    default: return LGF_OK;
+    }
+}
+
+int check_ctx(lgf_ctx *c) {
+    if (!c) return LGF_ERR_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    return LGF_OK;
+}
+
+// Pack caller links into FP64 working buffer 0, then F/theta of them.
+int eval_links64(lgf_ctx *c, const double *U, double &F, double &theta) {
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+    HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
+    HIPCHK(c, launch_div_reduce<double>(c->g, c->L64[0], c->D64[0], c->partials, c->status,
+                                        c->stream));
+    HIPCHK(c, launch_reduce_only(c->partials, c->nparts, c->reduce_out, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->reduce_host, c->reduce_out, 2 * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    F = c->reduce_host[0] * normF(c);
+    theta = c->reduce_host[1] * normT(c);
+    return LGF_OK;
+}
+
+int ensure_diff_scratch(lgf_ctx *c) {
+    if (!c->gaos) {
+        if (hipMalloc(&c->gaos, (size_t)4 * c->g.V * 9 * sizeof(double2)) != hipSuccess)
+            return fail(c, LGF_ERR_OOM, "out of device memory (differentiation scratch)");
+    }
+    if (!c->Lrot) {
+        if (hipMalloc(&c->Lrot, (size_t)24 * c->g.V * sizeof(double2)) != hipSuccess)
+            return fail(c, LGF_ERR_OOM, "out of device memory (differentiation scratch)");
+    }
+    return LGF_OK;
+}
+
+int sum_partials(lgf_ctx *c, double &A, double &B) {
+    HIPCHK(c, launch_reduce_only(c->partials, c->nparts, c->reduce_out, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->reduce_host, c->reduce_out, 2 * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    A = c->reduce_host[0];
+    B = c->reduce_host[1];
+    return LGF_OK;
+}
+
+template <class T>
+int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
+    using P = prec<T>;
+    const bool accG = std::is_same<T, float>::value;
+    HIPCHK(c, launch_pack_links<T>(U, P::links(c, 0), c->g.V, c->stream));
+    if (accG) HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->stream));
+    HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
+    HIPCHK(c, launch_div_reduce<T>(c->g, P::links(c, 0), P::field(c, 0), c->partials, c->status,
+                                   c->stream));
+    HIPCHK(c, launch_finalize(c->partials, c->nparts, c->status, normF(c), normT(c), 0.0, n + 1,
+                              0, c->histF, c->histT, HIST_CAP, c->stream));
+    std::vector<hipEvent_t> ev((size_t)n * 6);
+    for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
+    const T half_alpha = (T)(0.5 * alpha);
+    int rc = LGF_OK;
+    for (int it = 0; it < n && rc == LGF_OK; ++it) {
+        const int cur = it & 1;
+        void *D = P::field(c, cur);
+        hipEvent_t *e = &ev[(size_t)it * 6];
+        hipError_t err = hipSuccess;
+        auto chk = [&](hipError_t x) { if (err == hipSuccess) err = x; };
+        chk(hipEventRecord(e[0], c->stream));
+        chk(launch_fft_xy<T>(c->g, D, -1, P::tw(c), c->status, c->stream));
+        chk(hipEventRecord(e[1], c->stream));
+        chk(launch_fft_zt<T>(c->g, D, 0, P::tw(c), P::pt(c), (T)(c->p2max / (double)c->g.V),
+                             P::W(c), c->status, c->stream));
+        chk(hipEventRecord(e[2], c->stream));
+        chk(launch_fft_xy<T>(c->g, D, +1, P::tw(c), c->status, c->stream));
+        chk(hipEventRecord(e[3], c->stream));
+        chk(launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
+                             accG ? c->G32 : nullptr, half_alpha, c->partials, c->status,
+                             c->stream));
+        chk(hipEventRecord(e[4], c->stream));
+        chk(launch_finalize(c->partials, c->nparts, c->status, normF(c), normT(c), 0.0, n + 1, 1,
+                            c->histF, c->histT, HIST_CAP, c->stream));
+        chk(hipEventRecord(e[5], c->stream));
+        if (err != hipSuccess) rc = fail(c, LGF_ERR_DEVICE, hipGetErrorString(err));
+    }
+    if (rc == LGF_OK) {
+        hipError_t err = hipStreamSynchronize(c->stream);
+        for (int k = 0; k < 5; ++k) ms[k] = 0;
+        for (int it = 0; it < n && err == hipSuccess; ++it)
+            for (int k = 0; k < 5 && err == hipSuccess; ++k) {
+                float t = 0;
+                err = hipEventElapsedTime(&t, ev[(size_t)it * 6 + k], ev[(size_t)it * 6 + k + 1]);
+                ms[k] += t / n;
+            }
+        if (err != hipSuccess) rc = fail(c, LGF_ERR_DEVICE, hipGetErrorString(err));
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    return rc;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
+    if (!out || !L) return fail(nullptr, LGF_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (!shape_ok(L))
+        return fail(nullptr, LGF_ERR_ARG,
+                    "unsupported lattice extent (allowed: 2 3 4 6 8 12 16 24 32 48 64 96 128)");
+    {
+        geom g0{L[0], L[1], L[2], L[3], 1};
+        if (fft_zt_lds_bytes<double>(g0, 1) > 160 * 1024)
+            return fail(nullptr, LGF_ERR_ARG, "Lz*Lt too large for one (z,t) tile in LDS");
+    }
+    if (precision != LGF_FP64 && precision != LGF_MIXED)
+        return fail(nullptr, LGF_ERR_ARG, "precision must be LGF_FP64 or LGF_MIXED");
+    lgf_ctx *c = new (std::nothrow) lgf_ctx();
+    if (!c) return fail(nullptr, LGF_ERR_OOM, "host allocation failed");
+    c->g.Lx = L[0];
+    c->g.Ly = L[1];
+    c->g.Lz = L[2];
+    c->g.Lt = L[3];
+    c->g.V = (long)L[0] * L[1] * L[2] * L[3];
+    c->precision = precision;
+    c->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(nullptr, LGF_ERR_DEVICE, "no HIP device");
+    }
+    const long V = c->g.V;
+    c->nparts = site_blocks(V);
+    auto alloc = [&](void **p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; };
+    bool ok = true;
+    ok = ok && alloc((void **)&c->L64[0], (size_t)24 * V * sizeof(double2));
+    ok = ok && alloc((void **)&c->L64[1], (size_t)24 * V * sizeof(double2));
+    ok = ok && alloc((void **)&c->D64[0], (size_t)4 * V * sizeof(double2));
+    ok = ok && alloc((void **)&c->D64[1], (size_t)4 * V * sizeof(double2));
+    if (precision == LGF_MIXED) ok = ok && alloc((void **)&c->G32, (size_t)6 * V * sizeof(float2));
+    ok = ok && alloc((void **)&c->tw64, TW_M * sizeof(double2));
+    ok = ok && alloc((void **)&c->tw32, TW_M * sizeof(float2));
+    const int nt = L[0] + L[1] + L[2] + L[3];
+    ok = ok && alloc((void **)&c->pt64, nt * sizeof(double));
+    ok = ok && alloc((void **)&c->pt32, nt * sizeof(float));
+    ok = ok && alloc((void **)&c->partials, (size_t)2 * c->nparts * sizeof(double));
+    ok = ok && alloc((void **)&c->status, sizeof(dev_status));
+    ok = ok && alloc((void **)&c->reduce_out, 2 * sizeof(double));
+    ok = ok && alloc((void **)&c->histF, HIST_CAP * sizeof(double));
+    ok = ok && alloc((void **)&c->histT, HIST_CAP * sizeof(double));
+    ok = ok && hipHostMalloc((void **)&c->status_host, sizeof(dev_status), 0) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&c->reduce_host, 2 * sizeof(double), 0) == hipSuccess;
+    if (!ok) {
+        lgf_destroy(c);
+        return fail(nullptr, LGF_ERR_OOM, "out of device memory");
+    }
+    // FP32 working links live in the second FP64 buffer (2 x 12 floats per link)
+    c->L32[0] = reinterpret_cast<float2 *>(c->L64[1]);
+    c->L32[1] = reinterpret_cast<float2 *>(c->L64[1]) + (size_t)24 * V;
+
+    auto tw64 = make_twiddles<double2>();
+    auto tw32 = make_twiddles<float2>();
+    long double p2max = 0;
+    auto pt = make_p2_tables(c->g, p2max);
+    c->p2max = (double)p2max;
+    std::vector<double> pt64(pt.begin(), pt.end());
+    std::vector<float> pt32(pt.begin(), pt.end());
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpy(c->tw64, tw64.data(), TW_M * sizeof(double2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->tw32, tw32.data(), TW_M * sizeof(float2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->pt64, pt64.data(), nt * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->pt32, pt32.data(), nt * sizeof(float), hipMemcpyHostToDevice);
+    c->W64 = pick_W<double>(c->g);
+    c->W32 = pick_W<float>(c->g);
+    // best effort: a launch that still exceeds the limit reports its own error
+    (void)fft_zt_set_max_lds<double>(fft_zt_lds_bytes<double>(c->g, c->W64));
+    (void)fft_zt_set_max_lds<float>(fft_zt_lds_bytes<float>(c->g, c->W32));
+    if (e != hipSuccess) {
+        std::string m = std::string("initialisation failed: ") + hipGetErrorString(e);
+        lgf_destroy(c);
+        return fail(nullptr, LGF_ERR_DEVICE, m);
+    }
+    *out = c;
+    return LGF_OK;
+}
+
+void lgf_destroy(lgf_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    void *dev[] = {c->L64[0], c->L64[1], c->D64[0], c->D64[1], c->G32, c->tw64, c->tw32,
+                   c->pt64, c->pt32, c->partials, c->status, c->reduce_out, c->histF, c->histT,
+                   c->gaos, c->Lrot};
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    if (c->status_host) (void)hipHostFree(c->status_host);
+    if (c->reduce_host) (void)hipHostFree(c->reduce_host);
+    delete c;
+}
+
+int lgf_set_theta_switch(lgf_ctx *c, double theta_switch) {
+    if (!c || !(theta_switch > 0)) return fail(c, LGF_ERR_ARG, "theta_switch must be > 0");
+    c->theta_switch = theta_switch;
+    return LGF_OK;
+}
+
+static int solve(lgf_ctx *c, double *U, double alpha, double tol, int max_iter, lgf_result *res) {
+    Timer tm;
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    dev_status st{};
+    int n32 = 0, n64 = 0, code = ST_CONVERGED;
+    int cur64 = 0;
+    if (c->precision == LGF_MIXED) {
+        // FP32 phase on a downcast copy; G accumulates the applied transformation
+        HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g.V, c->stream));
+        HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->stream));
+        const double tol32 = std::max(tol, c->theta_switch);
+        rc = run_phase<float>(c, alpha, tol32, max_iter, true, 0, st);
+        if (rc) return rc;
+        n32 = st.n;
+        code = st.code;
+        // hand-over: U = G U0 G^dagger in FP64 (G reunitarised in FP64)
+        HIPCHK(c, launch_switch(c->g, c->G32, U, c->L64[0], c->stream));
+        if (code == ST_CONVERGED || code == ST_MAXITER) {
+            rc = run_phase<double>(c, alpha, tol, max_iter - n32, false, n32, st);
+            if (rc) return rc;
+            n64 = st.n;
+            code = st.code;
+            cur64 = n64 & 1;
+        }
+    } else {
+        HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+        rc = run_phase<double>(c, alpha, tol, max_iter, false, 0, st);
+        if (rc) return rc;
+        n64 = st.n;
+        code = st.code;
+        cur64 = n64 & 1;
+    }
+    HIPCHK(c, launch_unpack_links(c->L64[cur64], U, c->g.V, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->hist_len = n32 + n64 + 1;
+    const int out = status_to_code(code);
+    if (res) {
+        res->iterations = n32 + n64;
+        res->fp32_iterations = n32;
+        res->status = out;
+        res->F = st.F;
+        res->theta = st.theta;
+        res->seconds = tm.seconds();
+    }
+    if (out != LGF_OK) {
+        const char *m = out == LGF_NOT_CONVERGED ? "max_iter reached before theta < tol"
+                        : out == LGF_ERR_NONFINITE ? "theta became non-finite"
+                                                   : "theta rising: the iteration diverges";
+        c->err = m;
+    }
+    return out;
+}
+
+int lgf_fix(lgf_ctx *c, double *U, double alpha, double theta_tol, int max_iter, lgf_result *res) {
+    if (!c) return LGF_ERR_ARG;
+    if (!U) return fail(c, LGF_ERR_ARG, "U is NULL");
+    if (!(alpha > 0) || !(theta_tol > 0) || max_iter < 0)
+        return fail(c, LGF_ERR_ARG, "need alpha > 0, theta_tol > 0, max_iter >= 0");
+    return solve(c, U, alpha, theta_tol, max_iter, res);
+}
+
+int lgf_iterate(lgf_ctx *c, double *U, double alpha, int n_iter, lgf_result *res) {
+    if (!c) return LGF_ERR_ARG;
+    if (!U) return fail(c, LGF_ERR_ARG, "U is NULL");
+    if (!(alpha > 0) || n_iter < 0) return fail(c, LGF_ERR_ARG, "need alpha > 0, n_iter >= 0");
+    Timer tm;
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    dev_status st{};
+    int n32 = 0, n64 = 0, cur64 = 0;
+    if (c->precision == LGF_MIXED) {
+        HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g.V, c->stream));
+        HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->stream));
+        rc = run_phase<float>(c, alpha, 0.0, n_iter, true, 0, st);
+        if (rc) return rc;
+        n32 = st.n;
+        HIPCHK(c, launch_switch(c->g, c->G32, U, c->L64[0], c->stream));
+    } else {
+        HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+        rc = run_phase<double>(c, alpha, 0.0, n_iter, false, 0, st);
+        if (rc) return rc;
+        n64 = st.n;
+        cur64 = n64 & 1;
+    }
+    HIPCHK(c, launch_unpack_links(c->L64[cur64], U, c->g.V, c->stream));
+    double F = st.F, th = st.theta;
+    if (c->precision == LGF_MIXED) {
+        rc = eval_links64(c, U, F, th);
+        if (rc) return rc;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->hist_len = n32 + n64 + 1;
+    int out = (st.code == ST_NONFINITE) ? LGF_ERR_NONFINITE : LGF_OK;
+    if (res) {
+        res->iterations = n32 + n64;
+        res->fp32_iterations = n32;
+        res->status = out;
+        res->F = F;
+        res->theta = th;
+        res->seconds = tm.seconds();
+    }
+    return out;
+}
+
+int lgf_functional(lgf_ctx *c, const double *U, const double *g, double *F) {
+    if (!c) return LGF_ERR_ARG;
+    if (!U || !F) return fail(c, LGF_ERR_ARG, "null argument");
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!g) {
+        double th;
+        return eval_links64(c, U, *F, th);
+    }
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+    HIPCHK(c, launch_functional_g(c->g, c->L64[0], g, c->partials, c->stream));
+    double A, B;
+    rc = sum_partials(c, A, B);
+    if (rc) return rc;
+    *F = A * normF(c);
+    return LGF_OK;
+}
+
+int lgf_theta(lgf_ctx *c, const double *U, double *theta) {
+    if (!c) return LGF_ERR_ARG;
+    if (!U || !theta) return fail(c, LGF_ERR_ARG, "null argument");
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    double F;
+    return eval_links64(c, U, F, *theta);
+}
+
+int lgf_plaquette(lgf_ctx *c, const double *U, double *P) {
+    if (!c) return LGF_ERR_ARG;
+    if (!U || !P) return fail(c, LGF_ERR_ARG, "null argument");
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+    HIPCHK(c, launch_plaquette(c->g, c->L64[0], c->partials, c->stream));
+    double A, B;
+    rc = sum_partials(c, A, B);
+    if (rc) return rc;
+    *P = A / (6.0 * 3.0 * (double)c->g.V);
+    return LGF_OK;
+}
+
+int lgf_divergence(lgf_ctx *c, const double *U, double *Delta) {
+    if (!c) return LGF_ERR_ARG;
+    if (!U || !Delta) return fail(c, LGF_ERR_ARG, "null argument");
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+    HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
+    HIPCHK(c, launch_div_reduce<double>(c->g, c->L64[0], c->D64[0], c->partials, c->status,
+                                        c->stream));
+    HIPCHK(c, launch_matrix_from_field(c->D64[0], Delta, c->g.V, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LGF_OK;
+}
+
+int lgf_fourier_accelerate(lgf_ctx *c, const double *D, double *LD) {
+    if (!c) return LGF_ERR_ARG;
+    if (!D || !LD) return fail(c, LGF_ERR_ARG, "null argument");
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
+    HIPCHK(c, launch_field_from_matrix(D, c->D64[0], c->g.V, c->stream));
+    HIPCHK(c, launch_fft_xy<double>(c->g, c->D64[0], -1, c->tw64, c->status, c->stream));
+    HIPCHK(c, launch_fft_zt<double>(c->g, c->D64[0], 0, c->tw64, c->pt64,
+                                    c->p2max / (double)c->g.V, c->W64, c->status, c->stream));
+    HIPCHK(c, launch_fft_xy<double>(c->g, c->D64[0], +1, c->tw64, c->status, c->stream));
+    HIPCHK(c, launch_matrix_from_field(c->D64[0], LD, c->g.V, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LGF_OK;
+}
+
+int lgf_fft4d(lgf_ctx *c, double *fields, int sign) {
+    if (!c) return LGF_ERR_ARG;
+    if (!fields || (sign != 1 && sign != -1)) return fail(c, LGF_ERR_ARG, "bad argument");
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    double2 *F = reinterpret_cast<double2 *>(fields);
+    HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
+    if (sign < 0) {
+        HIPCHK(c, launch_fft_xy<double>(c->g, F, -1, c->tw64, c->status, c->stream));
+        HIPCHK(c, launch_fft_zt<double>(c->g, F, -1, c->tw64, c->pt64, 0.0, c->W64, c->status,
+                                        c->stream));
+        HIPCHK(c, launch_reorder_fields(c->g, F, c->D64[0], 1, c->stream));
+    } else {
+        HIPCHK(c, launch_reorder_fields(c->g, F, c->D64[0], 0, c->stream));
+        HIPCHK(c, hipMemcpyAsync(F, c->D64[0], (size_t)4 * c->g.V * sizeof(double2),
+                                 hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, launch_fft_zt<double>(c->g, F, +1, c->tw64, c->pt64, 0.0, c->W64, c->status,
+                                        c->stream));
+        HIPCHK(c, launch_fft_xy<double>(c->g, F, +1, c->tw64, c->status, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return LGF_OK;
+    }
+    HIPCHK(c, hipMemcpyAsync(F, c->D64[0], (size_t)4 * c->g.V * sizeof(double2),
+                             hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LGF_OK;
+}
+
+int lgf_functional_omega(lgf_ctx *c, const double *U, const double *omega, double *F) {
+    if (!c) return LGF_ERR_ARG;
+    if (!U || !omega || !F) return fail(c, LGF_ERR_ARG, "null argument");
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if ((rc = ensure_diff_scratch(c))) return rc;
+    HIPCHK(c, launch_expm_sites(omega, c->gaos, c->g.V, c->stream));
+    return lgf_functional(c, U, c->gaos, F);
+}
+
+int lgf_functional_omega_grad(lgf_ctx *c, const double *U, const double *omega, double *F,
+                              double *dF) {
+    if (!c) return LGF_ERR_ARG;
+    if (!U || !omega || !F || !dF) return fail(c, LGF_ERR_ARG, "null argument");
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if ((rc = ensure_diff_scratch(c))) return rc;
+    HIPCHK(c, launch_expm_sites(omega, c->gaos, c->g.V, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+    HIPCHK(c, launch_rotate_links(c->g, c->L64[0], c->gaos, c->Lrot, c->stream));
+    HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
+    HIPCHK(c, launch_div_reduce<double>(c->g, c->Lrot, c->D64[0], c->partials, c->status,
+                                        c->stream));
+    double A, B;
+    rc = sum_partials(c, A, B);
+    if (rc) return rc;
+    *F = A * normF(c);
+    HIPCHK(c, launch_omega_grad(c->g, c->D64[0], omega, dF, normF(c), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LGF_OK;
+}
+
+int lgf_theta_grad(lgf_ctx *c, const double *U, const double *eps, double *theta, double *dtheta) {
+    if (!c) return LGF_ERR_ARG;
+    if (!U || !theta) return fail(c, LGF_ERR_ARG, "null argument");
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if ((rc = ensure_diff_scratch(c))) return rc;
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+    const void *Lw = c->L64[0];
+    if (eps) {
+        HIPCHK(c, launch_expm_sites(eps, c->gaos, 4 * c->g.V, c->stream));
+        HIPCHK(c, launch_left_multiply_links(c->L64[0], c->gaos, c->Lrot, c->g.V, c->stream));
+        Lw = c->Lrot;
+    }
+    HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
+    HIPCHK(c, launch_div_reduce<double>(c->g, Lw, c->D64[0], c->partials, c->status, c->stream));
+    double A, B;
+    rc = sum_partials(c, A, B);
+    if (rc) return rc;
+    *theta = B * normT(c);
+    if (dtheta) {
+        HIPCHK(c, launch_theta_grad(c->g, Lw, c->D64[0], eps, dtheta, normT(c), c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return LGF_OK;
+}
+
+int lgf_profile(lgf_ctx *c, const double *U, double alpha, int n_iter, double *kernel_ms) {
+    if (!c) return LGF_ERR_ARG;
+    if (!U || !kernel_ms || n_iter < 1 || !(alpha > 0))
+        return fail(c, LGF_ERR_ARG, "need U, kernel_ms, n_iter >= 1, alpha > 0");
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    return c->precision == LGF_MIXED ? profile_impl<float>(c, U, alpha, n_iter, kernel_ms)
+                                     : profile_impl<double>(c, U, alpha, n_iter, kernel_ms);
+}
+
+int lgf_history(lgf_ctx *c, double *F, double *theta, int cap, int *count) {
+    if (!c || !count || cap < 0) return fail(c, LGF_ERR_ARG, "bad argument");
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    const int n = std::min(std::min(cap, c->hist_len), HIST_CAP);
+    if (n > 0 && F)
+        HIPCHK(c, hipMemcpy(F, c->histF, n * sizeof(double), hipMemcpyDeviceToHost));
+    if (n > 0 && theta)
+        HIPCHK(c, hipMemcpy(theta, c->histT, n * sizeof(double), hipMemcpyDeviceToHost));
+    *count = n;
+    return LGF_OK;
+}
+
+const char *lgf_last_error(const lgf_ctx *c) {
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,195 @@
+// Mixed-radix FFT building blocks for the 4D lattice transforms.
+//
+// * dft<N, DIR>: an N-point DFT held entirely in registers, fully unrolled,
+//   by recursive decimation in time with radix-4/3/2 butterflies.  Twiddles
+//   come from one table tw[j] = exp(-2 pi i j / TW_M), TW_M = 1152 = 2^7 3^2,
+//   so every supported extent divides TW_M; the table is built on the host in
+//   long double.  DIR = -1: exp(-2 pi i n k / N) (forward), +1: inverse.
+// * lds_axis_fft: transforms every column of a tile held in LDS along one
+//   lattice axis.  Extents up to 32 take one register pass per column.  Larger
+//   extents N = N1*N2 take two in-place Stockham-like passes; the forward
+//   result is then stored in a permuted order (position p = k1*N2 + k2 holds
+//   frequency k1 + N1*k2) that the matching inverse takes back to natural
+//   order.  Whatever sits between forward and inverse (the momentum-space
+//   scaling) only needs each position's frequency, see fft_freq_of_pos.
+#pragma once
+#include "su3.hpp"
+
+namespace lgf {
+
+constexpr int TW_M = 1152;
+
+__host__ __device__ constexpr int fft_split(int n) {
+    // N1 for a two-pass transform of extent n > 32 (n = N1 * N2, N1 <= N2)
+    return n == 48 ? 6 : n == 64 ? 8 : n == 96 ? 8 : n == 128 ? 8 : 1;
+}
+
+__host__ __device__ constexpr bool fft_supported(int n) {
+    return n == 2 || n == 3 || n == 4 || n == 6 || n == 8 || n == 12 || n == 16 || n == 24 ||
+           n == 32 || n == 48 || n == 64 || n == 96 || n == 128;
+}
+
+// frequency held at position p after a forward transform of extent n
+__host__ __device__ constexpr int fft_freq_of_pos(int n, int p) {
+    return n <= 32 ? p : (p / (n / fft_split(n))) + fft_split(n) * (p % (n / fft_split(n)));
+}
+
+template <int N, int DIR, class T>
+LGF_HD cpx<T> twiddle(const vec2_t<T> *__restrict__ tw, int k) {
+    // W_N^k = exp(DIR * 2 pi i k / N)
+    vec2_t<T> w = tw[((k % N) + N) % N * (TW_M / N)];
+    return DIR < 0 ? mk<T>(w.x, w.y) : mk<T>(w.x, -w.y);
+}
+
+template <int DIR, class T> LGF_HD void bfly2(cpx<T> *a) {
+    cpx<T> t = a[0];
+    a[0] = t + a[1];
+    a[1] = t - a[1];
+}
+
+template <int DIR, class T> LGF_HD void bfly3(cpx<T> *a) {
+    // W3 = exp(DIR 2 pi i / 3) = -1/2 + i DIR sqrt(3)/2
+    const T h = T(0.86602540378443864676372317075293618);
+    cpx<T> s = a[1] + a[2], d = a[1] - a[2];
+    cpx<T> m = a[0] - T(0.5) * s;
+    cpx<T> r = mk<T>(-T(DIR) * h * d.im, T(DIR) * h * d.re);  // i DIR h d
+    a[0] = a[0] + s;
+    a[1] = m + r;
+    a[2] = m - r;
+}
+
+template <int DIR, class T> LGF_HD void bfly4(cpx<T> *a) {
+    cpx<T> s02 = a[0] + a[2], d02 = a[0] - a[2];
+    cpx<T> s13 = a[1] + a[3], d13 = a[1] - a[3];
+    cpx<T> r = mk<T>(-T(DIR) * d13.im, T(DIR) * d13.re);  // i DIR d13
+    a[0] = s02 + s13;
+    a[2] = s02 - s13;
+    a[1] = d02 + r;
+    a[3] = d02 - r;
+}
+
+template <int N, int DIR, class T> LGF_HD void dft(cpx<T> *a, const vec2_t<T> *__restrict__ tw) {
+    if constexpr (N == 1) {
+        return;
+    } else if constexpr (N == 2) {
+        bfly2<DIR>(a);
+    } else if constexpr (N == 3) {
+        bfly3<DIR>(a);
+    } else if constexpr (N == 4) {
+        bfly4<DIR>(a);
+    } else {
+        constexpr int P = (N % 4 == 0) ? 4 : ((N % 3 == 0) ? 3 : 2);
+        constexpr int Q = N / P;
+        cpx<T> b[P][Q];
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int m = 0; m < Q; ++m) b[p][m] = a[m * P + p];
+#pragma unroll
+        for (int p = 0; p < P; ++p) dft<Q, DIR>(b[p], tw);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            cpx<T> t[P];
+            t[0] = b[0][k];
+#pragma unroll
+            for (int p = 1; p < P; ++p)
+                t[p] = (k == 0) ? b[p][k] : cmul(b[p][k], twiddle<N, DIR, T>(tw, p * k));
+            if constexpr (P == 4) bfly4<DIR>(t);
+            else if constexpr (P == 3) bfly3<DIR>(t);
+            else bfly2<DIR>(t);
+#pragma unroll
+            for (int s = 0; s < P; ++s) a[k + Q * s] = t[s];
+        }
+    }
+}
+
+// Column c of the tile: elements lds[base(c) + j*stride], j < N.
+// Must be called by every thread of the block (two-pass extents synchronise).
+template <int N, int DIR, class T, class Base>
+LGF_HD void lds_axis_fft_n(vec2_t<T> *lds, int ncols, int stride, Base base,
+                           const vec2_t<T> *__restrict__ tw) {
+    const int nthr = blockDim.x;
+    if constexpr (N <= 32) {
+        for (int c = threadIdx.x; c < ncols; c += nthr) {
+            const int b0 = base(c);
+            cpx<T> a[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) a[j] = ld<T>(lds + b0 + j * stride);
+            dft<N, DIR>(a, tw);
+#pragma unroll
+            for (int j = 0; j < N; ++j) st<T>(lds + b0 + j * stride, a[j]);
+        }
+    } else {
+        constexpr int N1 = fft_split(N), N2 = N / N1;
+        static_assert(N1 * N2 == N && N1 > 1, "unsupported extent");
+        if constexpr (DIR < 0) {
+            // pass 1: for each n2, DFT_N1 over n1 (stride N2), times W_N^(n2 k1)
+            for (int w = threadIdx.x; w < ncols * N2; w += nthr) {
+                const int c = w / N2, n2 = w - c * N2;
+                const int b0 = base(c) + n2 * stride;
+                cpx<T> a[N1];
+#pragma unroll
+                for (int j = 0; j < N1; ++j) a[j] = ld<T>(lds + b0 + j * N2 * stride);
+                dft<N1, DIR>(a, tw);
+#pragma unroll
+                for (int k1 = 1; k1 < N1; ++k1) a[k1] = cmul(a[k1], twiddle<N, DIR, T>(tw, n2 * k1));
+#pragma unroll
+                for (int j = 0; j < N1; ++j) st<T>(lds + b0 + j * N2 * stride, a[j]);
+            }
+            __syncthreads();
+            // pass 2: for each k1, DFT_N2 over n2 (contiguous block of N2)
+            for (int w = threadIdx.x; w < ncols * N1; w += nthr) {
+                const int c = w / N1, k1 = w - c * N1;
+                const int b0 = base(c) + k1 * N2 * stride;
+                cpx<T> a[N2];
+#pragma unroll
+                for (int j = 0; j < N2; ++j) a[j] = ld<T>(lds + b0 + j * stride);
+                dft<N2, DIR>(a, tw);
+#pragma unroll
+                for (int j = 0; j < N2; ++j) st<T>(lds + b0 + j * stride, a[j]);
+            }
+        } else {
+            // undo pass 2: for each k1, inverse DFT_N2 over the block, times W_N^(-n2 k1)
+            for (int w = threadIdx.x; w < ncols * N1; w += nthr) {
+                const int c = w / N1, k1 = w - c * N1;
+                const int b0 = base(c) + k1 * N2 * stride;
+                cpx<T> a[N2];
+#pragma unroll
+                for (int j = 0; j < N2; ++j) a[j] = ld<T>(lds + b0 + j * stride);
+                dft<N2, DIR>(a, tw);
+#pragma unroll
+                for (int n2 = 1; n2 < N2; ++n2) a[n2] = cmul(a[n2], twiddle<N, DIR, T>(tw, n2 * k1));
+#pragma unroll
+                for (int j = 0; j < N2; ++j) st<T>(lds + b0 + j * stride, a[j]);
+            }
+            __syncthreads();
+            // undo pass 1: for each n2, inverse DFT_N1 over k1 (stride N2)
+            for (int w = threadIdx.x; w < ncols * N2; w += nthr) {
+                const int c = w / N2, n2 = w - c * N2;
+                const int b0 = base(c) + n2 * stride;
+                cpx<T> a[N1];
+#pragma unroll
+                for (int j = 0; j < N1; ++j) a[j] = ld<T>(lds + b0 + j * N2 * stride);
+                dft<N1, DIR>(a, tw);
+#pragma unroll
+                for (int j = 0; j < N1; ++j) st<T>(lds + b0 + j * N2 * stride, a[j]);
+            }
+        }
+    }
+}
+
+// Runtime-extent dispatch.
+template <int DIR, class T, class Base>
+LGF_HD void lds_axis_fft(int n, vec2_t<T> *lds, int ncols, int stride, Base base,
+                         const vec2_t<T> *__restrict__ tw) {
+    switch (n) {
+#define LGF_CASE(NN) \
+    case NN: lds_axis_fft_n<NN, DIR, T>(lds, ncols, stride, base, tw); break;
+        LGF_CASE(2) LGF_CASE(3) LGF_CASE(4) LGF_CASE(6) LGF_CASE(8) LGF_CASE(12) LGF_CASE(16)
+        LGF_CASE(24) LGF_CASE(32) LGF_CASE(48) LGF_CASE(64) LGF_CASE(96) LGF_CASE(128)
+#undef LGF_CASE
+    default: break;
+    }
+}
+
+}  // namespace lgf

@@ -1,0 +1,1050 @@
+// HIP kernels of the Fourier-accelerated Landau gauge-fixing sweep (gfx950).
+//
+// One sweep (one gauge update) is four launches plus a one-block finalize:
+//   fft_xy(-1)  2D transform over the contiguous (x, y) planes, in place
+//   fft_zt(0)   2D transform over (z, t), scaling by p2max/(V p2), inverse
+//               (z, t) transform, in place: tiles of W consecutive xy-sites
+//   fft_xy(+1)  inverse (x, y) transform -> L Delta
+//   update      g = reunit(1 + alpha/2 L Delta) at x and its 8 neighbours,
+//               U'_mu(x) = g(x) U_mu(x) g(x+mu)^dagger (written), and the next
+//               Delta(x) from U'_mu(x) and the recomputed U'_mu(x-mu), with
+//               block partial sums of F and theta
+//   finalize    fixed-order sum of the partials, stopping test
+// Links are double-buffered (the update reads U_mu(x-mu) of other threads),
+// as are the Fourier fields.
+#include "fft.hpp"
+#include "kernels.hpp"
+#include "su3.hpp"
+
+namespace lgf {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+// Blocks are dispatched round-robin over the 8 XCDs; map them so that each
+// XCD (own L2) walks a contiguous range of sites and neighbour data is shared.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+struct nbr {
+    long p[4], m[4];  // s + mu, s - mu (periodic)
+};
+
+__device__ __forceinline__ nbr neighbours(const geom &g, long s) {
+    nbr n;
+    long r = s;
+    const int x = (int)(r % g.Lx); r /= g.Lx;
+    const int y = (int)(r % g.Ly); r /= g.Ly;
+    const int z = (int)(r % g.Lz);
+    const int t = (int)(r / g.Lz);
+    const long sy = g.Lx, sz = (long)g.Lx * g.Ly, stt = sz * g.Lz;
+    n.p[0] = (x == g.Lx - 1) ? s - (g.Lx - 1) : s + 1;
+    n.m[0] = (x == 0) ? s + (g.Lx - 1) : s - 1;
+    n.p[1] = (y == g.Ly - 1) ? s - (long)(g.Ly - 1) * sy : s + sy;
+    n.m[1] = (y == 0) ? s + (long)(g.Ly - 1) * sy : s - sy;
+    n.p[2] = (z == g.Lz - 1) ? s - (long)(g.Lz - 1) * sz : s + sz;
+    n.m[2] = (z == 0) ? s + (long)(g.Lz - 1) * sz : s - sz;
+    n.p[3] = (t == g.Lt - 1) ? s - (long)(g.Lt - 1) * stt : s + stt;
+    n.m[3] = (t == 0) ? s + (long)(g.Lt - 1) * stt : s - stt;
+    return n;
+}
+
+// Deterministic block sum of two doubles into partials[2*slot + {0,1}].
+template <int NT>
+__device__ __forceinline__ void block_sum2(double a, double b, double *partials, int slot) {
+    static_assert(NT % 64 == 0, "wave64 blocks");
+    __shared__ double sa[NT / 64], sb[NT / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sa[w] = a;
+        sb[w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double A = 0, B = 0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) {
+            A += sa[i];
+            B += sb[i];
+        }
+        partials[2 * slot] = A;
+        partials[2 * slot + 1] = B;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// layout conversion
+// ---------------------------------------------------------------------------
+
+// complex128 [4][V][3][3] -> SoA-12 of type T (rows 0,1)
+template <class T>
+__global__ void __launch_bounds__(256) k_pack_links(const double2 *__restrict__ U,
+                                                    vec2_t<T> *__restrict__ L, long V) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 4 * V) return;
+    const int mu = (int)(i / V);
+    const long s = i - (long)mu * V;
+    const double2 *u = U + i * 9;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        double2 v = u[k];
+        vec2_t<T> w;
+        w.x = (T)v.x;
+        w.y = (T)v.y;
+        L[((long)mu * 6 + k) * V + s] = w;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_unpack_links(const double2 *__restrict__ L,
+                                                      double2 *__restrict__ U, long V) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 4 * V) return;
+    const int mu = (int)(i / V);
+    const long s = i - (long)mu * V;
+    mat3<double> m = load_link<double>(L, V, mu, s);
+    double2 *u = U + i * 9;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
+}
+
+// anti-hermitian traceless matrix field (AoS 3x3 complex128) <-> 4 Fourier fields
+__global__ void k_field_from_matrix(const double2 *__restrict__ M, double2 *__restrict__ D, long V) {
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    const double2 *m = M + s * 9;
+    D[s] = m[1];
+    D[V + s] = m[2];
+    D[2 * V + s] = m[5];
+    D[3 * V + s] = make_double2(m[0].y, m[4].y);
+}
+
+__global__ void k_matrix_from_field(const double2 *__restrict__ D, double2 *__restrict__ M, long V) {
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    const double2 f0 = D[s], f1 = D[V + s], f2 = D[2 * V + s], f3 = D[3 * V + s];
+    double2 *m = M + s * 9;
+    m[0] = make_double2(0.0, f3.x);
+    m[1] = f0;
+    m[2] = f1;
+    m[3] = make_double2(-f0.x, f0.y);
+    m[4] = make_double2(0.0, f3.y);
+    m[5] = f2;
+    m[6] = make_double2(-f1.x, f1.y);
+    m[7] = make_double2(-f2.x, f2.y);
+    m[8] = make_double2(0.0, -(f3.x + f3.y));
+}
+
+// ---------------------------------------------------------------------------
+// divergence and reductions of given links (first sweep of a solve)
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ void __launch_bounds__(SITE_BLOCK)
+    k_div_reduce(geom g, const vec2_t<T> *__restrict__ L, vec2_t<T> *__restrict__ D,
+                 double *__restrict__ partials, const dev_status *__restrict__ status) {
+    if (status->done) return;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const long s = (long)b * SITE_BLOCK + threadIdx.x;
+    double fs = 0, ts = 0;
+    if (s < g.V) {
+        const nbr n = neighbours(g, s);
+        xacc<T> X;
+        xacc_zero(X);
+        T tr = 0;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            mat3<T> u = load_link<T>(L, g.V, mu, s);
+            tr += retrace(u);
+            xacc_add(X, u, T(-1));
+            mat3<T> um = load_link<T>(L, g.V, mu, n.m[mu]);
+            xacc_add(X, um, T(1));
+        }
+        cpx<T> f0, f1, f2, f3;
+        ts = (double)delta_pack(X, f0, f1, f2, f3);
+        fs = (double)tr;
+        st<T>(D + s, f0);
+        st<T>(D + g.V + s, f1);
+        st<T>(D + 2 * g.V + s, f2);
+        st<T>(D + 3 * g.V + s, f3);
+    }
+    block_sum2<SITE_BLOCK>(fs, ts, partials, b);
+}
+
+// ---------------------------------------------------------------------------
+// fused update + next divergence
+// ---------------------------------------------------------------------------
+
+template <class T, bool ACC_G>
+__global__ void __launch_bounds__(SITE_BLOCK)
+    k_update(geom g, const vec2_t<T> *__restrict__ Lin, vec2_t<T> *__restrict__ Lout,
+             const vec2_t<T> *__restrict__ LD, vec2_t<T> *__restrict__ Dout,
+             vec2_t<T> *__restrict__ G, T c, double *__restrict__ partials,
+             const dev_status *__restrict__ status) {
+    if (status->done) return;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const long s = (long)b * SITE_BLOCK + threadIdx.x;
+    double fs = 0, ts = 0;
+    if (s < g.V) {
+        const nbr n = neighbours(g, s);
+        const mat3<T> g0 = gauge_from_field<T>(LD, g.V, s, c);
+        xacc<T> X;
+        xacc_zero(X);
+        T tr = 0;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const mat3<T> gp = gauge_from_field<T>(LD, g.V, n.p[mu], c);
+            const mat3<T> u = load_link<T>(Lin, g.V, mu, s);
+            const mat3<T> un = mul_abcd(g0, u, gp);
+            store_link<T>(Lout, g.V, mu, s, un);
+            tr += retrace(un);
+            xacc_add(X, un, T(-1));
+            const mat3<T> gm = gauge_from_field<T>(LD, g.V, n.m[mu], c);
+            const mat3<T> um = load_link<T>(Lin, g.V, mu, n.m[mu]);
+            const mat3<T> umn = mul_abcd(gm, um, g0);
+            xacc_add(X, umn, T(1));
+        }
+        cpx<T> f0, f1, f2, f3;
+        ts = (double)delta_pack(X, f0, f1, f2, f3);
+        fs = (double)tr;
+        st<T>(Dout + s, f0);
+        st<T>(Dout + g.V + s, f1);
+        st<T>(Dout + 2 * g.V + s, f2);
+        st<T>(Dout + 3 * g.V + s, f3);
+        if constexpr (ACC_G) {
+            // G(x) <- g(x) G(x), rows 0,1 kept (12 reals)
+            mat3<T> G0;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) G0.e[k / 3][k % 3] = ld<T>(G + (long)k * g.V + s);
+            rebuild_row2(G0);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    cpx<T> acc = cmul(g0.e[i][0], G0.e[0][j]);
+                    acc = acc + cmul(g0.e[i][1], G0.e[1][j]);
+                    acc = acc + cmul(g0.e[i][2], G0.e[2][j]);
+                    st<T>(G + (long)(3 * i + j) * g.V + s, acc);
+                }
+        }
+    }
+    block_sum2<SITE_BLOCK>(fs, ts, partials, b);
+}
+
+// ---------------------------------------------------------------------------
+// (x, y) plane transform: one plane of one field per block, LDS [y][x+1]
+// ---------------------------------------------------------------------------
+
+constexpr int XY_BLOCK = 64;
+
+template <class T, int DIR>
+__global__ void __launch_bounds__(XY_BLOCK)
+    k_fft_xy(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
+             const dev_status *__restrict__ status) {
+    if (status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
+    const int Lx = g.Lx, Ly = g.Ly, P = Lx + 1;
+    const long Lxy = (long)Lx * Ly;
+    vec2_t<T> *plane = D + (long)blockIdx.y * g.V + (long)blockIdx.x * Lxy;
+    for (int i = threadIdx.x; i < Lxy; i += XY_BLOCK) {
+        const int y = i / Lx, x = i - y * Lx;
+        lds[y * P + x] = plane[i];
+    }
+    __syncthreads();
+    auto rows = [P](int c) { return c * P; };
+    auto cols = [](int c) { return c; };
+    if (DIR < 0) {
+        lds_axis_fft<DIR, T>(Lx, lds, Ly, 1, rows, tw);
+        __syncthreads();
+        lds_axis_fft<DIR, T>(Ly, lds, Lx, P, cols, tw);
+    } else {
+        lds_axis_fft<DIR, T>(Ly, lds, Lx, P, cols, tw);
+        __syncthreads();
+        lds_axis_fft<DIR, T>(Lx, lds, Ly, 1, rows, tw);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < Lxy; i += XY_BLOCK) {
+        const int y = i / Lx, x = i - y * Lx;
+        plane[i] = lds[y * P + x];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// (z, t) transform of W consecutive xy-sites of one field per block.
+// LDS element (w, z, t) at t*PT + z*W + w, PT = Lz*W + ZT_PAD.
+// MODE 0: forward z,t; scale by p2max/(V p2); inverse t,z.  -1 / +1: one way.
+// ---------------------------------------------------------------------------
+
+constexpr int ZT_BLOCK = 256;
+constexpr int ZT_PAD = 4;
+
+template <int N, class T, class Base, class Scale>
+__device__ __forceinline__ void t_fwd_scale_inv(vec2_t<T> *lds, int ncols, int stride, Base base,
+                                                Scale scale, const vec2_t<T> *__restrict__ tw) {
+    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+        const int b0 = base(c);
+        cpx<T> a[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) a[j] = ld<T>(lds + b0 + j * stride);
+        dft<N, -1>(a, tw);
+#pragma unroll
+        for (int j = 0; j < N; ++j) a[j] = scale(c, j) * a[j];
+        dft<N, +1>(a, tw);
+#pragma unroll
+        for (int j = 0; j < N; ++j) st<T>(lds + b0 + j * stride, a[j]);
+    }
+}
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(ZT_BLOCK)
+    k_fft_zt(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
+             const T *__restrict__ ptab, T p2max_over_V, int W,
+             const dev_status *__restrict__ status) {
+    if (status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
+    const int Lz = g.Lz, Lt = g.Lt;
+    const long Lxy = (long)g.Lx * g.Ly;
+    const int PT = Lz * W + ZT_PAD;
+    const long s0 = (long)xcd_block(blockIdx.x, gridDim.x) * W;
+    const int Wt = (int)min((long)W, Lxy - s0);
+    vec2_t<T> *F = D + (long)blockIdx.y * g.V;
+    const int nel = W * Lz * Lt;
+    for (int i = threadIdx.x; i < nel; i += ZT_BLOCK) {
+        const int w = i % W, zt = i / W, z = zt % Lz, t = zt / Lz;
+        vec2_t<T> v;
+        v.x = 0;
+        v.y = 0;
+        if (w < Wt) v = F[(long)zt * Lxy + s0 + w];
+        lds[t * PT + z * W + w] = v;
+    }
+    __syncthreads();
+    auto zcol = [W, PT](int c) { return (c / W) * PT + (c % W); };  // c = w + W*t
+    auto tcol = [W](int c) { return c; };                          // c = w + W*z
+    if (MODE <= 0) {
+        lds_axis_fft<-1, T>(Lz, lds, W * Lt, W, zcol, tw);
+        __syncthreads();
+    }
+    if (MODE == 0) {
+        const T *px = ptab, *py = ptab + g.Lx, *pz = ptab + g.Lx + g.Ly,
+                *pt = ptab + g.Lx + g.Ly + g.Lz;
+        const int Lx = g.Lx;
+        auto scale = [=](int c, int j) -> T {
+            const int w = c % W, z = c / W;
+            const long sxy = s0 + w;
+            if (sxy >= Lxy) return T(0);  // padding column of a ragged tile
+            const int x = (int)(sxy % Lx), y = (int)(sxy / Lx);
+            const T p2 = (px[x] + py[y]) + (pz[z] + pt[j]);
+            return p2 == T(0) ? T(0) : p2max_over_V / p2;
+        };
+        switch (Lt) {
+#define LGF_TCASE(NN) \
+    case NN: t_fwd_scale_inv<NN, T>(lds, W * Lz, PT, tcol, scale, tw); break;
+            LGF_TCASE(2) LGF_TCASE(3) LGF_TCASE(4) LGF_TCASE(6) LGF_TCASE(8) LGF_TCASE(12)
+            LGF_TCASE(16) LGF_TCASE(24) LGF_TCASE(32)
+#undef LGF_TCASE
+        default: {
+            lds_axis_fft<-1, T>(Lt, lds, W * Lz, PT, tcol, tw);
+            __syncthreads();
+            for (int i = threadIdx.x; i < W * Lz * Lt; i += ZT_BLOCK) {
+                const int c = i % (W * Lz), j = i / (W * Lz);
+                vec2_t<T> *p = lds + j * PT + c;
+                const T f = scale(c, j);
+                vec2_t<T> v = *p;
+                v.x *= f;
+                v.y *= f;
+                *p = v;
+            }
+            __syncthreads();
+            lds_axis_fft<+1, T>(Lt, lds, W * Lz, PT, tcol, tw);
+        } break;
+        }
+        __syncthreads();
+    } else {
+        lds_axis_fft<MODE, T>(Lt, lds, W * Lz, PT, tcol, tw);
+        __syncthreads();
+    }
+    if (MODE >= 0) {
+        lds_axis_fft<+1, T>(Lz, lds, W * Lt, W, zcol, tw);
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < nel; i += ZT_BLOCK) {
+        const int w = i % W, zt = i / W, z = zt % Lz, t = zt / Lz;
+        if (w < Wt) F[(long)zt * Lxy + s0 + w] = lds[t * PT + z * W + w];
+    }
+}
+
+// reorder 4 fields between natural index order and transform-position order
+__global__ void k_reorder(geom g, const double2 *__restrict__ in, double2 *__restrict__ out,
+                          int to_natural) {
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V) return;
+    long r = s;
+    const int a0 = (int)(r % g.Lx); r /= g.Lx;
+    const int a1 = (int)(r % g.Ly); r /= g.Ly;
+    const int a2 = (int)(r % g.Lz);
+    const int a3 = (int)(r / g.Lz);
+    // s is a position index; its natural (frequency) index:
+    const int f0 = fft_freq_of_pos(g.Lx, a0), f1 = fft_freq_of_pos(g.Ly, a1),
+              f2 = fft_freq_of_pos(g.Lz, a2), f3 = fft_freq_of_pos(g.Lt, a3);
+    const long sn = f0 + (long)g.Lx * (f1 + (long)g.Ly * (f2 + (long)g.Lz * f3));
+    for (int f = 0; f < 4; ++f) {
+        if (to_natural) out[f * g.V + sn] = in[f * g.V + s];
+        else out[f * g.V + s] = in[f * g.V + sn];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// finalize: fixed-order sum of block partials and the stopping test
+// ---------------------------------------------------------------------------
+
+constexpr int FIN_BLOCK = 256;
+
+__device__ __forceinline__ void fixed_order_sum(const double *__restrict__ partials, int nparts,
+                                                double &A, double &B) {
+    double a = 0, b = 0;
+    for (int i = threadIdx.x; i < nparts; i += FIN_BLOCK) {
+        a += partials[2 * i];
+        b += partials[2 * i + 1];
+    }
+    __shared__ double sa[FIN_BLOCK], sb[FIN_BLOCK];
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int h = FIN_BLOCK / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sa[threadIdx.x] += sa[threadIdx.x + h];
+            sb[threadIdx.x] += sb[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    A = sa[0];
+    B = sb[0];
+}
+
+__global__ void __launch_bounds__(FIN_BLOCK)
+    k_finalize(const double *__restrict__ partials, int nparts, dev_status *__restrict__ status,
+               double normF, double normT, double tol, int max_iter, int increment,
+               double *__restrict__ histF, double *__restrict__ histT, int hist_cap) {
+    if (status->done) return;
+    double A, B;
+    fixed_order_sum(partials, nparts, A, B);
+    if (threadIdx.x != 0) return;
+    const double F = A * normF, th = B * normT;
+    dev_status st = *status;
+    if (increment) st.n += 1;
+    const int h = st.hist_base + st.n;
+    if (h < hist_cap) {
+        histF[h] = F;
+        histT[h] = th;
+    }
+    st.F = F;
+    st.theta = th;
+    if (!isfinite(th) || !isfinite(F)) {
+        st.done = 1;
+        st.code = ST_NONFINITE;
+    } else if (th < tol) {
+        st.done = 1;
+        st.code = ST_CONVERGED;
+    } else if (st.n >= max_iter) {
+        st.done = 1;
+        st.code = ST_MAXITER;
+    } else {
+        st.rises = (st.n > 0 && th > st.theta_prev) ? st.rises + 1 : 0;
+        if (st.rises >= DIVERGE_RISES) {
+            st.done = 1;
+            st.code = ST_DIVERGING;
+        }
+    }
+    st.theta_prev = th;
+    *status = st;
+}
+
+__global__ void k_status_reset(dev_status *status, int hist_base) {
+    dev_status st;
+    st.F = 0;
+    st.theta = 0;
+    st.theta_prev = 0;
+    st.n = 0;
+    st.done = 0;
+    st.code = ST_RUNNING;
+    st.rises = 0;
+    st.hist_base = hist_base;
+    st.pad = 0;
+    *status = st;
+}
+
+__global__ void __launch_bounds__(FIN_BLOCK)
+    k_reduce_only(const double *__restrict__ partials, int nparts, double *out2) {
+    double A, B;
+    fixed_order_sum(partials, nparts, A, B);
+    if (threadIdx.x == 0) {
+        out2[0] = A;
+        out2[1] = B;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// mixed precision: accumulated transformation and the hand-over to FP64
+// ---------------------------------------------------------------------------
+
+__global__ void k_g_identity(float2 *__restrict__ G, long V) {
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) G[(long)k * V + s] = make_float2(k == 0 || k == 4 ? 1.f : 0.f, 0.f);
+}
+
+__device__ __forceinline__ mat3<double> load_G_fp64(const float2 *__restrict__ G, long V, long s) {
+    mat3<double> m;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float2 v = G[(long)k * V + s];
+        m.e[k / 3][k % 3] = mk<double>(v.x, v.y);
+    }
+    reunitarise(m);
+    return m;
+}
+
+// U_mu(x) = G(x) U0_mu(x) G(x+mu)^dagger in FP64, G reunitarised in FP64
+__global__ void __launch_bounds__(SITE_BLOCK)
+    k_switch(geom g, const float2 *__restrict__ G, const double2 *__restrict__ U0,
+             double2 *__restrict__ L) {
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V) return;
+    const nbr n = neighbours(g, s);
+    const mat3<double> g0 = load_G_fp64(G, g.V, s);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const mat3<double> gp = load_G_fp64(G, g.V, n.p[mu]);
+        mat3<double> u;
+        const double2 *p = U0 + ((long)mu * g.V + s) * 9;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) u.e[k / 3][k % 3] = mk<double>(p[k].x, p[k].y);
+        rebuild_row2(u);
+        store_link<double>(L, g.V, mu, s, mul_abcd(g0, u, gp));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// gauge-invariant checks and F_U[g]
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(SITE_BLOCK)
+    k_plaquette(geom g, const double2 *__restrict__ L, double *__restrict__ partials) {
+    const long s = (long)blockIdx.x * SITE_BLOCK + threadIdx.x;
+    double acc = 0;
+    if (s < g.V) {
+        const nbr n = neighbours(g, s);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const mat3<double> umu = load_link<double>(L, g.V, mu, s);
+#pragma unroll
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                const mat3<double> a = load_link<double>(L, g.V, nu, n.p[mu]);   // U_nu(x+mu)
+                const mat3<double> b = load_link<double>(L, g.V, mu, n.p[nu]);   // U_mu(x+nu)
+                const mat3<double> c = load_link<double>(L, g.V, nu, s);         // U_nu(x)
+                // Re Tr[umu a b^+ c^+] = Re Tr[P Q^+] = Re sum_ij P_ij conj(Q_ij),
+                // P = umu a, Q = c b
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) {
+                        cpx<double> p = mk<double>(0, 0), q = mk<double>(0, 0);
+                        for (int k = 0; k < 3; ++k) {
+                            p = p + cmul(umu.e[i][k], a.e[k][j]);
+                            q = q + cmul(c.e[i][k], b.e[k][j]);
+                        }
+                        acc += p.re * q.re + p.im * q.im;
+                    }
+            }
+        }
+    }
+    block_sum2<SITE_BLOCK>(acc, 0.0, partials, blockIdx.x);
+}
+
+// sum_mu Re Tr[g(x) U_mu(x) g(x+mu)^dagger], g full 3x3 AoS (NULL: identity)
+__global__ void __launch_bounds__(SITE_BLOCK)
+    k_functional_g(geom g, const double2 *__restrict__ L, const double2 *__restrict__ ga,
+                   double *__restrict__ partials) {
+    const long s = (long)blockIdx.x * SITE_BLOCK + threadIdx.x;
+    double acc = 0;
+    if (s < g.V) {
+        const nbr n = neighbours(g, s);
+        mat3<double> g0;
+        for (int k = 0; k < 9; ++k) g0.e[k / 3][k % 3] = mk<double>(ga[s * 9 + k].x, ga[s * 9 + k].y);
+        for (int mu = 0; mu < 4; ++mu) {
+            mat3<double> gp;
+            const long sp = n.p[mu];
+            for (int k = 0; k < 9; ++k) gp.e[k / 3][k % 3] = mk<double>(ga[sp * 9 + k].x, ga[sp * 9 + k].y);
+            const mat3<double> u = load_link<double>(L, g.V, mu, s);
+            // Re Tr[g0 u gp^+] = Re sum_ij (g0 u)_ij conj(gp_ij)
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    cpx<double> p = mk<double>(0, 0);
+                    for (int k = 0; k < 3; ++k) p = p + cmul(g0.e[i][k], u.e[k][j]);
+                    acc += p.re * gp.e[i][j].re + p.im * gp.e[i][j].im;
+                }
+        }
+    }
+    block_sum2<SITE_BLOCK>(acc, 0.0, partials, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// differentiation
+// ---------------------------------------------------------------------------
+
+// X = i sum_a w_a lambda_a / 2
+__device__ __forceinline__ mat3<double> su3_alg(const double *w) {
+    const double r3 = 0.57735026918962576451;  // 1/sqrt(3)
+    // H = sum_a w_a lambda_a, X = (i/2) H
+    cpx<double> H[3][3];
+    H[0][0] = mk<double>(w[2] + w[7] * r3, 0);
+    H[1][1] = mk<double>(-w[2] + w[7] * r3, 0);
+    H[2][2] = mk<double>(-2 * w[7] * r3, 0);
+    H[0][1] = mk<double>(w[0], -w[1]);
+    H[1][0] = mk<double>(w[0], w[1]);
+    H[0][2] = mk<double>(w[3], -w[4]);
+    H[2][0] = mk<double>(w[3], w[4]);
+    H[1][2] = mk<double>(w[5], -w[6]);
+    H[2][1] = mk<double>(w[5], w[6]);
+    mat3<double> X;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) X.e[i][j] = mk<double>(-0.5 * H[i][j].im, 0.5 * H[i][j].re);
+    return X;
+}
+
+__device__ __forceinline__ mat3<double> mat_mul_full(const mat3<double> &a, const mat3<double> &b) {
+    mat3<double> r;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            cpx<double> acc = cmul(a.e[i][0], b.e[0][j]);
+            acc = acc + cmul(a.e[i][1], b.e[1][j]);
+            acc = acc + cmul(a.e[i][2], b.e[2][j]);
+            r.e[i][j] = acc;
+        }
+    return r;
+}
+
+// exp(X) for anti-hermitian X: halve until |X| <= 1/2, Taylor to 24 terms, square back
+__device__ mat3<double> expm3(mat3<double> X) {
+    double nrm = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) nrm += norm2(X.e[i][j]);
+    nrm = sqrt(nrm);
+    int sq = 0;
+    while (nrm > 0.5 && sq < 60) {
+        nrm *= 0.5;
+        ++sq;
+    }
+    const double sc = ldexp(1.0, -sq);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) X.e[i][j] = sc * X.e[i][j];
+    mat3<double> E, term;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) E.e[i][j] = term.e[i][j] = mk<double>(i == j ? 1.0 : 0.0, 0.0);
+    for (int k = 1; k <= 24; ++k) {
+        term = mat_mul_full(term, X);
+        const double inv = 1.0 / k;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                term.e[i][j] = inv * term.e[i][j];
+                E.e[i][j] = E.e[i][j] + term.e[i][j];
+            }
+    }
+    for (int i = 0; i < sq; ++i) E = mat_mul_full(E, E);
+    return E;
+}
+
+__global__ void k_expm_sites(const double *__restrict__ w, double2 *__restrict__ out, long n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double ww[8];
+    for (int a = 0; a < 8; ++a) ww[a] = w[i * 8 + a];
+    const mat3<double> E = expm3(su3_alg(ww));
+    for (int k = 0; k < 9; ++k) out[i * 9 + k] = make_double2(E.e[k / 3][k % 3].re, E.e[k / 3][k % 3].im);
+}
+
+__device__ __forceinline__ mat3<double> load_full(const double2 *__restrict__ a, long i) {
+    mat3<double> m;
+    for (int k = 0; k < 9; ++k) m.e[k / 3][k % 3] = mk<double>(a[i * 9 + k].x, a[i * 9 + k].y);
+    return m;
+}
+
+// links Lout_mu(x) = g(x) Lin_mu(x) g(x+mu)^dagger (g full AoS, unitary)
+__global__ void __launch_bounds__(SITE_BLOCK)
+    k_rotate_links(geom g, const double2 *__restrict__ Lin, const double2 *__restrict__ ga,
+                   double2 *__restrict__ Lout) {
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V) return;
+    const nbr n = neighbours(g, s);
+    const mat3<double> g0 = load_full(ga, s);
+    for (int mu = 0; mu < 4; ++mu) {
+        const mat3<double> gp = load_full(ga, n.p[mu]);
+        const mat3<double> u = load_link<double>(Lin, g.V, mu, s);
+        store_link<double>(Lout, g.V, mu, s, mul_abcd(g0, u, gp));
+    }
+}
+
+// Lout_mu(x) = E_mu(x) Lin_mu(x), E full AoS [4][V]
+__global__ void k_left_multiply(const double2 *__restrict__ Lin, const double2 *__restrict__ E,
+                                double2 *__restrict__ Lout, long V) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 4 * V) return;
+    const int mu = (int)(i / V);
+    const long s = i - (long)mu * V;
+    const mat3<double> e = load_full(E, i);
+    const mat3<double> u = load_link<double>(Lin, V, mu, s);
+    mat3<double> r = mat_mul_full(e, u);
+    store_link<double>(Lout, V, mu, s, r);
+}
+
+// Im Tr[lambda_a W], a = 0..7
+__device__ __forceinline__ void im_tr_lambda(const mat3<double> &W, double y[8]) {
+    const double r3 = 0.57735026918962576451;
+    y[0] = W.e[1][0].im + W.e[0][1].im;
+    y[1] = W.e[0][1].re - W.e[1][0].re;
+    y[2] = W.e[0][0].im - W.e[1][1].im;
+    y[3] = W.e[2][0].im + W.e[0][2].im;
+    y[4] = W.e[0][2].re - W.e[2][0].re;
+    y[5] = W.e[2][1].im + W.e[1][2].im;
+    y[6] = W.e[1][2].re - W.e[2][1].re;
+    y[7] = (W.e[0][0].im + W.e[1][1].im - 2 * W.e[2][2].im) * r3;
+}
+
+// out = sum_k (A^T)^k v / (k+1)!,  A[b][a] = coefficient of i T^b in [i w.T, i T^a]
+//     = -sum_c f_abc w_c  (SU(3) structure constants).
+// This is the transpose of the derivative of the exponential map, so for
+// g = exp(i w.T): d/dw^a = sum_b S[b][a] (derivative along i T^b g).
+__device__ void dexp_transpose_apply(const double *w, const double *v, double *out) {
+    double A[8][8];
+    for (int i = 0; i < 8; ++i)
+        for (int j = 0; j < 8; ++j) A[i][j] = 0;
+    const int tri[9][3] = {{0, 1, 2}, {0, 3, 6}, {0, 5, 4}, {1, 3, 5}, {1, 4, 6},
+                           {2, 3, 4}, {2, 6, 5}, {3, 4, 7}, {5, 6, 7}};
+    const double h3 = 0.86602540378443864676;
+    const double fv[9] = {1.0, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5, h3, h3};
+    for (int t = 0; t < 9; ++t) {
+        const int a = tri[t][0], b = tri[t][1], c = tri[t][2];
+        const double v0 = fv[t];
+        // f_ijk w_k contributes -f_ijk w_k to A[j][i] for every permutation (i,j,k)
+        A[b][a] -= v0 * w[c];  // (a,b,c) +
+        A[c][b] -= v0 * w[a];  // (b,c,a) +
+        A[a][c] -= v0 * w[b];  // (c,a,b) +
+        A[a][b] += v0 * w[c];  // (b,a,c) -
+        A[c][a] += v0 * w[b];  // (a,c,b) -
+        A[b][c] += v0 * w[a];  // (c,b,a) -
+    }
+    double term[8], acc[8];
+    for (int i = 0; i < 8; ++i) term[i] = acc[i] = v[i];
+    for (int k = 1; k <= 80; ++k) {
+        double nt[8];
+        double mx = 0;
+        for (int a = 0; a < 8; ++a) {
+            double s = 0;
+            for (int b = 0; b < 8; ++b) s += A[b][a] * term[b];
+            nt[a] = s / (k + 1);
+            mx = fmax(mx, fabs(nt[a]));
+        }
+        double ma = 0;
+        for (int a = 0; a < 8; ++a) {
+            term[a] = nt[a];
+            acc[a] += nt[a];
+            ma = fmax(ma, fabs(acc[a]));
+        }
+        if (mx <= 1e-18 * ma) break;
+    }
+    for (int a = 0; a < 8; ++a) out[a] = acc[a];
+}
+
+// dF/domega from Delta of the transformed links (D64 fields) and omega
+__global__ void k_omega_grad(geom g, const double2 *__restrict__ D, const double *__restrict__ om,
+                             double *__restrict__ dF, double normF) {
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V) return;
+    const double2 f0 = D[s], f1 = D[g.V + s], f2 = D[2 * g.V + s], f3 = D[3 * g.V + s];
+    mat3<double> M;
+    M.e[0][0] = mk<double>(0, f3.x);
+    M.e[0][1] = mk<double>(f0.x, f0.y);
+    M.e[0][2] = mk<double>(f1.x, f1.y);
+    M.e[1][0] = mk<double>(-f0.x, f0.y);
+    M.e[1][1] = mk<double>(0, f3.y);
+    M.e[1][2] = mk<double>(f2.x, f2.y);
+    M.e[2][0] = mk<double>(-f1.x, f1.y);
+    M.e[2][1] = mk<double>(-f2.x, f2.y);
+    M.e[2][2] = mk<double>(0, -(f3.x + f3.y));
+    double y[8], G[8], w[8], out[8];
+    im_tr_lambda(M, y);
+    // G^b = -(i/4) normF Tr[lambda_b Delta] = (normF/4) Im Tr[lambda_b Delta]
+    for (int b = 0; b < 8; ++b) G[b] = 0.25 * normF * y[b];
+    for (int a = 0; a < 8; ++a) w[a] = om[s * 8 + a];
+    dexp_transpose_apply(w, G, out);
+    for (int a = 0; a < 8; ++a) dF[s * 8 + a] = out[a];
+}
+
+// dtheta/deps^a_mu(x) at links L (already exp(i eps.T) U); eps may be NULL
+__global__ void __launch_bounds__(SITE_BLOCK)
+    k_theta_grad(geom g, const double2 *__restrict__ L, const double2 *__restrict__ D,
+                 const double *__restrict__ eps, double *__restrict__ dth, double normT) {
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V) return;
+    const nbr n = neighbours(g, s);
+    auto fieldmat = [&](long q) {
+        const double2 f0 = D[q], f1 = D[g.V + q], f2 = D[2 * g.V + q], f3 = D[3 * g.V + q];
+        mat3<double> M;
+        M.e[0][0] = mk<double>(0, f3.x);
+        M.e[0][1] = mk<double>(f0.x, f0.y);
+        M.e[0][2] = mk<double>(f1.x, f1.y);
+        M.e[1][0] = mk<double>(-f0.x, f0.y);
+        M.e[1][1] = mk<double>(0, f3.y);
+        M.e[1][2] = mk<double>(f2.x, f2.y);
+        M.e[2][0] = mk<double>(-f1.x, f1.y);
+        M.e[2][1] = mk<double>(-f2.x, f2.y);
+        M.e[2][2] = mk<double>(0, -(f3.x + f3.y));
+        return M;
+    };
+    const mat3<double> d0 = fieldmat(s);
+    for (int mu = 0; mu < 4; ++mu) {
+        const mat3<double> dp = fieldmat(n.p[mu]);
+        mat3<double> Dd;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) Dd.e[i][j] = dp.e[i][j] - d0.e[i][j];
+        const mat3<double> u = load_link<double>(L, g.V, mu, s);
+        mat3<double> ud;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) ud.e[i][j] = conjg(u.e[j][i]);
+        const mat3<double> W1 = mat_mul_full(u, Dd), W2 = mat_mul_full(Dd, ud);
+        mat3<double> W;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) W.e[i][j] = W1.e[i][j] + W2.e[i][j];
+        double y[8], out[8];
+        im_tr_lambda(W, y);
+        for (int a = 0; a < 8; ++a) y[a] *= normT;
+        const long o = ((long)mu * g.V + s) * 8;
+        if (eps) {
+            double w[8];
+            for (int a = 0; a < 8; ++a) w[a] = eps[o + a];
+            dexp_transpose_apply(w, y, out);
+        } else {
+            for (int a = 0; a < 8; ++a) out[a] = y[a];
+        }
+        for (int a = 0; a < 8; ++a) dth[o + a] = out[a];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <class T>
+hipError_t launch_pack_links(const double *Uaos, void *L, long V, hipStream_t st) {
+    k_pack_links<T><<<nblk(4 * V, 256), 256, 0, st>>>(reinterpret_cast<const double2 *>(Uaos),
+                                                      static_cast<vec2_t<T> *>(L), V);
+    return hipGetLastError();
+}
+template hipError_t launch_pack_links<double>(const double *, void *, long, hipStream_t);
+template hipError_t launch_pack_links<float>(const double *, void *, long, hipStream_t);
+
+hipError_t launch_unpack_links(const void *L64, double *Uaos, long V, hipStream_t st) {
+    k_unpack_links<<<nblk(4 * V, 256), 256, 0, st>>>(static_cast<const double2 *>(L64),
+                                                     reinterpret_cast<double2 *>(Uaos), V);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *partials,
+                             const dev_status *status, hipStream_t st) {
+    k_div_reduce<T><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
+        g, static_cast<const vec2_t<T> *>(L), static_cast<vec2_t<T> *>(D), partials, status);
+    return hipGetLastError();
+}
+template hipError_t launch_div_reduce<double>(const geom &, const void *, void *, double *,
+                                              const dev_status *, hipStream_t);
+template hipError_t launch_div_reduce<float>(const geom &, const void *, void *, double *,
+                                             const dev_status *, hipStream_t);
+
+template <class T>
+hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void *LD, void *Dout,
+                         void *G, T c, double *partials, const dev_status *status, hipStream_t st) {
+    if (G)
+        k_update<T, true><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
+            g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout),
+            static_cast<const vec2_t<T> *>(LD), static_cast<vec2_t<T> *>(Dout),
+            static_cast<vec2_t<T> *>(G), c, partials, status);
+    else
+        k_update<T, false><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
+            g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout),
+            static_cast<const vec2_t<T> *>(LD), static_cast<vec2_t<T> *>(Dout), nullptr, c,
+            partials, status);
+    return hipGetLastError();
+}
+template hipError_t launch_update<double>(const geom &, const void *, void *, const void *, void *,
+                                          void *, double, double *, const dev_status *, hipStream_t);
+template hipError_t launch_update<float>(const geom &, const void *, void *, const void *, void *,
+                                         void *, float, double *, const dev_status *, hipStream_t);
+
+template <class T>
+hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const dev_status *status,
+                         hipStream_t st) {
+    dim3 grid((unsigned)(g.Lz * g.Lt), 4);
+    const size_t lds = (size_t)g.Ly * (g.Lx + 1) * sizeof(vec2_t<T>);
+    if (dir < 0)
+        k_fft_xy<T, -1><<<grid, XY_BLOCK, lds, st>>>(g, static_cast<vec2_t<T> *>(D),
+                                                     static_cast<const vec2_t<T> *>(tw), status);
+    else
+        k_fft_xy<T, +1><<<grid, XY_BLOCK, lds, st>>>(g, static_cast<vec2_t<T> *>(D),
+                                                     static_cast<const vec2_t<T> *>(tw), status);
+    return hipGetLastError();
+}
+template hipError_t launch_fft_xy<double>(const geom &, void *, int, const void *,
+                                          const dev_status *, hipStream_t);
+template hipError_t launch_fft_xy<float>(const geom &, void *, int, const void *,
+                                         const dev_status *, hipStream_t);
+
+template <class T> size_t fft_zt_lds_bytes(const geom &g, int W) {
+    return (size_t)g.Lt * ((size_t)g.Lz * W + ZT_PAD) * sizeof(vec2_t<T>);
+}
+template size_t fft_zt_lds_bytes<double>(const geom &, int);
+template size_t fft_zt_lds_bytes<float>(const geom &, int);
+
+template <class T> hipError_t fft_zt_set_max_lds(size_t bytes) {
+    hipError_t e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_zt<T, 0>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_zt<T, -1>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_zt<T, 1>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+template hipError_t fft_zt_set_max_lds<double>(size_t);
+template hipError_t fft_zt_set_max_lds<float>(size_t);
+
+template <class T>
+hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const T *ptab,
+                         T p2max_over_V, int W, const dev_status *status, hipStream_t st) {
+    const long Lxy = (long)g.Lx * g.Ly;
+    dim3 grid((unsigned)((Lxy + W - 1) / W), 4);
+    const size_t lds = fft_zt_lds_bytes<T>(g, W);
+    auto Dp = static_cast<vec2_t<T> *>(D);
+    auto twp = static_cast<const vec2_t<T> *>(tw);
+    if (mode == 0)
+        k_fft_zt<T, 0><<<grid, ZT_BLOCK, lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W, status);
+    else if (mode < 0)
+        k_fft_zt<T, -1><<<grid, ZT_BLOCK, lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W, status);
+    else
+        k_fft_zt<T, 1><<<grid, ZT_BLOCK, lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W, status);
+    return hipGetLastError();
+}
+template hipError_t launch_fft_zt<double>(const geom &, void *, int, const void *, const double *,
+                                          double, int, const dev_status *, hipStream_t);
+template hipError_t launch_fft_zt<float>(const geom &, void *, int, const void *, const float *,
+                                         float, int, const dev_status *, hipStream_t);
+
+hipError_t launch_reorder_fields(const geom &g, const double2 *in, double2 *out, int to_natural,
+                                 hipStream_t st) {
+    k_reorder<<<nblk(g.V, 256), 256, 0, st>>>(g, in, out, to_natural);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *partials, int nparts, dev_status *status, double normF,
+                           double normT, double tol, int max_iter, int increment, double *histF,
+                           double *histT, int hist_cap, hipStream_t st) {
+    k_finalize<<<1, FIN_BLOCK, 0, st>>>(partials, nparts, status, normF, normT, tol, max_iter,
+                                        increment, histF, histT, hist_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_status_reset(dev_status *status, int hist_base, hipStream_t st) {
+    k_status_reset<<<1, 1, 0, st>>>(status, hist_base);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_only(const double *partials, int nparts, double *out2, hipStream_t st) {
+    k_reduce_only<<<1, FIN_BLOCK, 0, st>>>(partials, nparts, out2);
+    return hipGetLastError();
+}
+
+hipError_t launch_g_identity(void *G32, long V, hipStream_t st) {
+    k_g_identity<<<nblk(V, 256), 256, 0, st>>>(static_cast<float2 *>(G32), V);
+    return hipGetLastError();
+}
+
+hipError_t launch_switch(const geom &g, const void *G32, const double *U0aos, void *L64,
+                         hipStream_t st) {
+    k_switch<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, static_cast<const float2 *>(G32),
+                                                      reinterpret_cast<const double2 *>(U0aos),
+                                                      static_cast<double2 *>(L64));
+    return hipGetLastError();
+}
+
+hipError_t launch_field_from_matrix(const double *Maos, void *D64, long V, hipStream_t st) {
+    k_field_from_matrix<<<nblk(V, 256), 256, 0, st>>>(reinterpret_cast<const double2 *>(Maos),
+                                                      static_cast<double2 *>(D64), V);
+    return hipGetLastError();
+}
+
+hipError_t launch_matrix_from_field(const void *D64, double *Maos, long V, hipStream_t st) {
+    k_matrix_from_field<<<nblk(V, 256), 256, 0, st>>>(static_cast<const double2 *>(D64),
+                                                      reinterpret_cast<double2 *>(Maos), V);
+    return hipGetLastError();
+}
+
+hipError_t launch_plaquette(const geom &g, const void *L64, double *partials, hipStream_t st) {
+    k_plaquette<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, static_cast<const double2 *>(L64),
+                                                         partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_functional_g(const geom &g, const void *L64, const double *gaos,
+                               double *partials, hipStream_t st) {
+    k_functional_g<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
+        g, static_cast<const double2 *>(L64), reinterpret_cast<const double2 *>(gaos), partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_expm_sites(const double *omega, double *gaos, long n, hipStream_t st) {
+    k_expm_sites<<<nblk(n, 128), 128, 0, st>>>(omega, reinterpret_cast<double2 *>(gaos), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_rotate_links(const geom &g, const void *Lin, const double *gaos, void *Lout,
+                               hipStream_t st) {
+    k_rotate_links<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
+        g, static_cast<const double2 *>(Lin), reinterpret_cast<const double2 *>(gaos),
+        static_cast<double2 *>(Lout));
+    return hipGetLastError();
+}
+
+hipError_t launch_left_multiply_links(const void *Lin, const double *eaos, void *Lout, long V,
+                                      hipStream_t st) {
+    k_left_multiply<<<nblk(4 * V, 256), 256, 0, st>>>(static_cast<const double2 *>(Lin),
+                                                      reinterpret_cast<const double2 *>(eaos),
+                                                      static_cast<double2 *>(Lout), V);
+    return hipGetLastError();
+}
+
+hipError_t launch_omega_grad(const geom &g, const void *D64, const double *omega, double *dF,
+                             double normF, hipStream_t st) {
+    k_omega_grad<<<nblk(g.V, 128), 128, 0, st>>>(g, static_cast<const double2 *>(D64), omega, dF,
+                                                 normF);
+    return hipGetLastError();
+}
+
+hipError_t launch_theta_grad(const geom &g, const void *L64, const void *D64, const double *eps,
+                             double *dth, double normT, hipStream_t st) {
+    k_theta_grad<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
+        g, static_cast<const double2 *>(L64), static_cast<const double2 *>(D64), eps, dth, normT);
+    return hipGetLastError();
+}
+
+}  // namespace lgf

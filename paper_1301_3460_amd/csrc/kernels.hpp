@@ -1,0 +1,87 @@
+// Launch interface between the C-ABI host code and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace lgf {
+
+// Solver state kept on the device so that a batch of sweeps can be enqueued
+// without reading anything back; every sweep kernel returns at once when
+// `done` is set.
+struct dev_status {
+    double F, theta, theta_prev;
+    int n;          // gauge updates applied in the current phase
+    int done;       // 1: stop (kernels become no-ops)
+    int code;       // 0 running, 1 converged, 4 max_iter, 5 non-finite, 6 diverging
+    int rises;      // consecutive iterations with rising theta
+    int hist_base;  // history slot of this phase's n = 0
+    int pad;
+};
+
+enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXITER = 4, ST_NONFINITE = 5, ST_DIVERGING = 6 };
+constexpr int DIVERGE_RISES = 8;
+
+struct geom {
+    int Lx, Ly, Lz, Lt;
+    long V;
+};
+
+constexpr int SITE_BLOCK = 256;  // threads per block of the site kernels
+inline int site_blocks(long V) { return (int)((V + SITE_BLOCK - 1) / SITE_BLOCK); }
+
+// All launchers enqueue on `st` and return hipGetLastError().
+template <class T>
+hipError_t launch_pack_links(const double *Uaos, void *L, long V, hipStream_t st);
+hipError_t launch_unpack_links(const void *L64, double *Uaos, long V, hipStream_t st);
+
+template <class T>
+hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *partials,
+                             const dev_status *status, hipStream_t st);
+
+template <class T>
+hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void *LD, void *Dout,
+                         void *G, T c, double *partials, const dev_status *status, hipStream_t st);
+
+// mode: -1 forward only, +1 inverse only (x,y pass: direction)
+template <class T>
+hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw,
+                         const dev_status *status, hipStream_t st);
+// mode 0: forward, scale by p2max/(V p2), inverse; -1: forward only; +1: inverse only
+template <class T>
+hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const T *ptab,
+                         T p2max_over_V, int W, const dev_status *status, hipStream_t st);
+template <class T> size_t fft_zt_lds_bytes(const geom &g, int W);
+template <class T> hipError_t fft_zt_set_max_lds(size_t bytes);
+
+// natural <-> transform-position order of 4 fields (dir -1: positions -> natural)
+hipError_t launch_reorder_fields(const geom &g, const double2 *in, double2 *out, int to_natural,
+                                 hipStream_t st);
+
+hipError_t launch_finalize(const double *partials, int nparts, dev_status *status, double normF,
+                           double normT, double tol, int max_iter, int increment, double *histF,
+                           double *histT, int hist_cap, hipStream_t st);
+hipError_t launch_status_reset(dev_status *status, int hist_base, hipStream_t st);
+hipError_t launch_reduce_only(const double *partials, int nparts, double *out2, hipStream_t st);
+
+hipError_t launch_g_identity(void *G32, long V, hipStream_t st);
+hipError_t launch_switch(const geom &g, const void *G32, const double *U0aos, void *L64,
+                         hipStream_t st);
+
+hipError_t launch_field_from_matrix(const double *Maos, void *D64, long V, hipStream_t st);
+hipError_t launch_matrix_from_field(const void *D64, double *Maos, long V, hipStream_t st);
+
+hipError_t launch_plaquette(const geom &g, const void *L64, double *partials, hipStream_t st);
+hipError_t launch_functional_g(const geom &g, const void *L64, const double *gaos,
+                               double *partials, hipStream_t st);
+
+// differentiation (FP64)
+hipError_t launch_expm_sites(const double *omega, double *gaos, long n, hipStream_t st);
+hipError_t launch_rotate_links(const geom &g, const void *Lin, const double *gaos, void *Lout,
+                               hipStream_t st);
+hipError_t launch_left_multiply_links(const void *Lin, const double *eaos, void *Lout, long V,
+                                      hipStream_t st);
+hipError_t launch_omega_grad(const geom &g, const void *D64, const double *omega, double *dF,
+                             double normF, hipStream_t st);
+hipError_t launch_theta_grad(const geom &g, const void *L64, const void *D64, const double *eps,
+                             double *dth, double normT, hipStream_t st);
+
+}  // namespace lgf

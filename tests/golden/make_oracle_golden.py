@@ -1,0 +1,59 @@
+"""Write oracle reference values for the full-size solves.
+
+Calls only ``oracle`` (the plain FP64 CPU implementation) and ``inputs`` (the
+seeded generators).  Output: ``tests/golden/oracle_<name>.json`` holding, per
+disorder level, the seed, the iteration count, F and theta of the solved
+links, the plaquette before and after, and the per-iteration F/theta history.
+Nothing here comes from the GPU library.
+
+    python tests/golden/make_oracle_golden.py 32^4
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import inputs  # noqa: E402
+import oracle  # noqa: E402
+
+WORKLOADS = {
+    "32^4": {"L": (32, 32, 32, 32), "eps": [0.6, 0.45, 0.35], "alpha": 0.08, "tol": 1e-15},
+    "8^4": {"L": (8, 8, 8, 8), "eps": [0.5], "alpha": 0.08, "tol": 1e-12},
+}
+
+
+def main(name: str) -> None:
+    w = WORKLOADS[name]
+    out = {"workload": name, "L": w["L"], "alpha": w["alpha"], "tol": w["tol"],
+           "threads": oracle.get_threads(), "runs": []}
+    for eps in w["eps"]:
+        seed = inputs.CONFIG_SEEDS[(name, eps)]
+        U, _ = inputs.make_config(w["L"], eps, seed)
+        P0 = oracle.plaquette(U)
+        t0 = time.time()
+        r = oracle.fix(U, w["alpha"], w["tol"], 2000)
+        dt = time.time() - t0
+        mu, md = oracle.unitarity(r["U"])
+        run = {"eps": eps, "seed": seed, "status": r["status"], "iterations": r["iterations"],
+               "F": r["F"], "theta": r["theta"], "plaquette_in": P0,
+               "plaquette_out": oracle.plaquette(r["U"]), "unitarity": mu, "det": md,
+               "F_hist": list(r["F_hist"]), "theta_hist": list(r["theta_hist"]),
+               "seconds": dt}
+        print(f"{name} eps={eps}: {r['iterations']} it, F={r['F']:.15f}, theta={r['theta']:.3e}, "
+              f"{dt:.1f} s", flush=True)
+        out["runs"].append(run)
+        del U, r
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                        f"oracle_{name.replace('^', '')}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else "32^4")

@@ -1,0 +1,128 @@
+"""Full solves on the GPU against the FP64 oracle, status handling, mixed precision."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+ALPHA = 0.08
+
+
+def gpu(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def cpu(t):
+    return t.detach().cpu().numpy()
+
+
+def _check_solution(Uout, Uin, tol, F):
+    """The oracle re-measures the returned links."""
+    assert oracle.theta(Uout) < tol
+    assert oracle.F(Uout) == pytest.approx(F, abs=1e-13)
+    assert abs(oracle.plaquette(Uout) - oracle.plaquette(Uin)) < 1e-12
+    mu, md = oracle.unitarity(Uout)
+    assert mu < 1e-13 and md < 1e-13
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("L,eps,seed,tol", [
+    ((8, 8, 8, 8), 0.5, inputs.CONFIG_SEEDS[("8^4", 0.5)], 1e-12),
+    ((4, 4, 4, 4), 0.5, inputs.CONFIG_SEEDS[("4^4", 0.5)], 1e-15),
+    ((4, 6, 8, 12), 0.45, 77, 1e-15),
+    ((6, 6, 6, 6), 0.6, 78, 1e-14),
+])
+def test_solve_matches_oracle(lgf_gpu, L, eps, seed, tol, precision):
+    U, _ = inputs.make_config(L, eps, seed)
+    ref = oracle.fix(U, ALPHA, tol, 1000)
+    assert ref["status"] == 0
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, ALPHA, tol, precision=precision, max_iter=1000)
+    assert r.status == 0
+    Uout = cpu(Ug)
+    _check_solution(Uout, U, tol, r.F)
+    assert abs(r.F - ref["F"]) < 1e-12
+    if precision == "fp64":
+        assert abs(r.iterations - ref["iterations"]) <= 1
+    else:
+        assert r.fp32_iterations > 0 and r.iterations > r.fp32_iterations
+
+
+def test_history_monotone_and_consistent(lgf_gpu):
+    U, _ = inputs.make_config((8, 8, 8, 8), 0.5, 31)
+    Ug = gpu(U)
+    ctx = lgf_gpu._ctx(Ug)
+    r = ctx.fix(Ug, ALPHA, 1e-13, 500)
+    F, T = ctx.history()
+    assert len(F) == r.iterations + 1
+    assert np.all(np.diff(F) >= -1e-15)
+    assert T[-1] == r.theta and T[-1] < 1e-13 and np.all(T[:-1] >= 1e-13)
+    ref = oracle.fix(U, ALPHA, 1e-13, 500)
+    n = min(len(F), len(ref["F_hist"]))
+    assert np.max(np.abs(F[:n] - ref["F_hist"][:n])) < 1e-12
+
+
+def test_converged_input_takes_zero_updates(lgf_gpu):
+    U = inputs.unit_config((4, 4, 4, 4))
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, ALPHA, 1e-15)
+    assert r.status == 0 and r.iterations == 0 and r.theta == 0.0 and r.F == 1.0
+    assert np.array_equal(cpu(Ug), U)
+
+
+def test_max_iter_reached(lgf_gpu):
+    U, _ = inputs.make_config((4, 4, 4, 4), 0.5, 32)
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, ALPHA, 1e-15, max_iter=3)
+    assert r.status == lgf_gpu.LGF_NOT_CONVERGED and r.iterations == 3
+    assert np.max(np.abs(cpu(Ug) - oracle.iterate(U, ALPHA, 3))) < 1e-13
+    assert r.theta == pytest.approx(oracle.theta(cpu(Ug)), rel=1e-12)
+    r0 = lgf_gpu.fix(gpu(U), ALPHA, 1e-15, max_iter=0)
+    assert r0.status == lgf_gpu.LGF_NOT_CONVERGED and r0.iterations == 0
+
+
+def test_nonfinite_input(lgf_gpu):
+    U, _ = inputs.make_config((4, 4, 4, 4), 0.5, 33)
+    U[1, 0, 1, 2, 3, 0, 1] = np.nan
+    r = lgf_gpu.fix(gpu(U), ALPHA, 1e-15)
+    assert r.status == lgf_gpu.LGF_ERR_NONFINITE and r.iterations == 0
+
+
+def test_too_large_step_diverges(lgf_gpu):
+    """alpha above 2/p2max = 0.125 amplifies the divergence (|1 - 16 alpha| > 1)."""
+    U = inputs.abelian_config((8, 8, 8, 8), 1e-4, 34)
+    r = lgf_gpu.fix(gpu(U), 0.2, 1e-15, max_iter=100)
+    assert r.status == lgf_gpu.LGF_DIVERGING and r.iterations < 100
+
+
+def test_bad_arguments_raise(lgf_gpu):
+    import torch
+
+    U = gpu(inputs.unit_config((4, 4, 4, 4)))
+    with pytest.raises(lgf_gpu.LgfError):
+        lgf_gpu.fix(U, -0.08, 1e-15)
+    with pytest.raises(lgf_gpu.LgfError):
+        lgf_gpu.fix(U, 0.08, 0.0)
+    with pytest.raises(ValueError):
+        lgf_gpu.fix(U.to(torch.complex64), 0.08, 1e-15)
+    with pytest.raises(ValueError):
+        lgf_gpu.fix(U.cpu(), 0.08, 1e-15)
+
+
+def test_mixed_iterate_applies_accumulated_transformation(lgf_gpu):
+    """A mixed-precision context runs FP32 sweeps and applies the accumulated
+    transformation to the FP64 input: the result is exactly on the gauge orbit
+    and close (FP32 accuracy) to the FP64 trajectory."""
+    U, _ = inputs.make_config((8, 8, 8, 8), 0.5, 35)
+    Ug = gpu(U)
+    lgf_gpu.iterate(Ug, ALPHA, 6, precision="mixed")
+    out = cpu(Ug)
+    assert abs(oracle.plaquette(out) - oracle.plaquette(U)) < 1e-13
+    mu, _ = oracle.unitarity(out)
+    assert mu < 1e-14
+    ref = oracle.iterate(U, ALPHA, 6)
+    assert np.max(np.abs(out - ref)) < 1e-4

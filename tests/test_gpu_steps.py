@@ -83,7 +83,11 @@ def test_link_storage_round_trip(lgf_gpu):
     assert r.iterations == 0
     out = cpu(Ug)
     assert np.array_equal(out[..., :2, :], U[..., :2, :])
-    assert np.max(np.abs(out[..., 2, :] - U[..., 2, :])) < 1e-15
+    rebuilt = np.conj(np.cross(U[..., 0, :], U[..., 1, :]))
+    assert np.max(np.abs(out[..., 2, :] - rebuilt)) < 1e-15
+    # and within the input's own distance from SU(3) of its stored row 2
+    mu, _ = oracle.unitarity(U)
+    assert np.max(np.abs(out[..., 2, :] - U[..., 2, :])) < 2 * mu + 1e-15
 
 
 @pytest.mark.parametrize("L", [(4, 4, 4, 4), (8, 8, 8, 8), (4, 6, 8, 12), (2, 3, 4, 6),

@@ -102,8 +102,13 @@ def random_near_identity_links(L, eps: float, rng: np.random.Generator) -> np.nd
     Draw order: h[mu][t][z][y][x][a] (one ``standard_normal`` call)."""
     shp = (4,) + site_shape(L)
     h = rng.standard_normal(shp + (8,))
-    H = np.tensordot(h, GELL_MANN, axes=([-1], [0])) * (0.5 * eps)
-    return _expi_hermitian(H.reshape(-1, 3, 3)).reshape(shp + (3, 3))
+    hf = h.reshape(-1, 8)
+    out = np.empty((hf.shape[0], 3, 3), dtype=np.complex128)
+    chunk = 1 << 20  # fixed, so results never depend on the machine
+    for a in range(0, hf.shape[0], chunk):
+        H = np.tensordot(hf[a:a + chunk], GELL_MANN, axes=([-1], [0])) * (0.5 * eps)
+        out[a:a + chunk] = _expi_hermitian(H)
+    return out.reshape(shp + (3, 3))
 
 
 def _haar_from_ginibre(Z: np.ndarray) -> np.ndarray:

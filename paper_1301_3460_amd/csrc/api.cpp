@@ -52,7 +52,7 @@ struct lgf_ctx {
     float2 *tw32 = nullptr;
     double *pt64 = nullptr;
     float *pt32 = nullptr;
-    int W64 = 1, W32 = 1;
+    zt_plan zt64{}, zt32{};
     // reductions and control
     double *partials = nullptr;
     int nparts = 0;
@@ -62,6 +62,7 @@ struct lgf_ctx {
     double *reduce_host = nullptr;      // pinned [2]
     double *histF = nullptr, *histT = nullptr;
     int hist_len = 0;
+    unsigned *counter = nullptr;  // last-block counter of the sweep kernels
     // differentiation scratch (allocated on first use)
     double *gaos = nullptr;   // V*9 complex or 4V*9 complex (link exponentials)
     double2 *Lrot = nullptr;  // SoA-12 FP64 links
@@ -86,6 +87,24 @@ int fail(lgf_ctx *c, int code, const std::string &msg) {
 
 double normF(const lgf_ctx *c) { return 1.0 / (4.0 * 3.0 * (double)c->g.V); }
 double normT(const lgf_ctx *c) { return 1.0 / (3.0 * (double)c->g.V); }
+
+// Stopping-test parameters for the sweep kernels (enabled == false: the
+// kernel only writes block partials).
+fin_params finp(const lgf_ctx *c, bool enabled, double tol = 0, int max_iter = 0,
+                int increment = 0) {
+    fin_params f;
+    f.normF = normF(c);
+    f.normT = normT(c);
+    f.tol = tol;
+    f.max_iter = max_iter;
+    f.increment = increment;
+    f.hist_cap = HIST_CAP;
+    f.enabled = enabled ? 1 : 0;
+    f.histF = c->histF;
+    f.histT = c->histT;
+    f.counter = c->counter;
+    return f;
+}
 
 // tw[j] = exp(-2 pi i j / TW_M), long double
 template <class V2> std::vector<V2> make_twiddles() {
@@ -118,13 +137,6 @@ std::vector<long double> make_p2_tables(const geom &g, long double &p2max) {
     return t;
 }
 
-template <class T> int pick_W(const geom &g) {
-    const long Lxy = (long)g.Lx * g.Ly;
-    int W = 16;
-    while (W > 1 && ((long)W > Lxy || fft_zt_lds_bytes<T>(g, W) > ZT_LDS_BUDGET)) W >>= 1;
-    return W;
-}
-
 bool shape_ok(const int L[4]) {
     for (int mu = 0; mu < 4; ++mu)
         if (!fft_supported(L[mu])) return false;
@@ -139,18 +151,19 @@ template <> struct prec<double> {
     static void *field(lgf_ctx *c, int i) { return c->D64[i]; }
     static const void *tw(lgf_ctx *c) { return c->tw64; }
     static const double *pt(lgf_ctx *c) { return c->pt64; }
-    static int W(lgf_ctx *c) { return c->W64; }
+    static const zt_plan &W(lgf_ctx *c) { return c->zt64; }
 };
 template <> struct prec<float> {
     static void *links(lgf_ctx *c, int i) { return c->L32[i]; }
     static void *field(lgf_ctx *c, int i) { return c->D64[i]; }
     static const void *tw(lgf_ctx *c) { return c->tw32; }
     static const float *pt(lgf_ctx *c) { return c->pt32; }
-    static int W(lgf_ctx *c) { return c->W32; }
+    static const zt_plan &W(lgf_ctx *c) { return c->zt32; }
 };
 
 // One Fourier-accelerated sweep from links/field buffer `cur` into `cur^1`.
-template <class T> hipError_t enqueue_sweep(lgf_ctx *c, int cur, T half_alpha, bool accG) {
+template <class T>
+hipError_t enqueue_sweep(lgf_ctx *c, int cur, T half_alpha, bool accG, const fin_params &fp) {
     using P = prec<T>;
     hipError_t e;
     void *D = P::field(c, cur);
@@ -160,7 +173,8 @@ template <class T> hipError_t enqueue_sweep(lgf_ctx *c, int cur, T half_alpha, b
         return e;
     if ((e = launch_fft_xy<T>(c->g, D, +1, P::tw(c), c->status, c->stream)) != hipSuccess) return e;
     return launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
-                            accG ? c->G32 : nullptr, half_alpha, c->partials, c->status, c->stream);
+                            accG ? c->G32 : nullptr, half_alpha, c->partials, c->status, fp,
+                            c->stream);
 }
 
 int read_status(lgf_ctx *c, dev_status &out) {
@@ -179,9 +193,7 @@ int run_phase(lgf_ctx *c, double alpha, double tol, int max_iter, bool accG, int
     using P = prec<T>;
     HIPCHK(c, launch_status_reset(c->status, hist_base, c->stream));
     HIPCHK(c, launch_div_reduce<T>(c->g, P::links(c, 0), P::field(c, 0), c->partials, c->status,
-                                   c->stream));
-    HIPCHK(c, launch_finalize(c->partials, c->nparts, c->status, normF(c), normT(c), tol, max_iter,
-                              0, c->histF, c->histT, HIST_CAP, c->stream));
+                                   finp(c, true, tol, max_iter, 0), c->stream));
     int rc = read_status(c, st);
     if (rc) return rc;
     const T half_alpha = (T)(0.5 * alpha);
@@ -204,9 +216,7 @@ int run_phase(lgf_ctx *c, double alpha, double tol, int max_iter, bool accG, int
         n_prev = st.n;
         for (int i = 0; i < k; ++i) {
             const int cur = (enq + i) & 1;
-            HIPCHK(c, enqueue_sweep<T>(c, cur, half_alpha, accG));
-            HIPCHK(c, launch_finalize(c->partials, c->nparts, c->status, normF(c), normT(c), tol,
-                                      max_iter, 1, c->histF, c->histT, HIST_CAP, c->stream));
+            HIPCHK(c, enqueue_sweep<T>(c, cur, half_alpha, accG, finp(c, true, tol, max_iter, 1)));
         }
         enq += k;
         rc = read_status(c, st);
@@ -236,7 +246,7 @@ int eval_links64(lgf_ctx *c, const double *U, double &F, double &theta) {
     HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<double>(c->g, c->L64[0], c->D64[0], c->partials, c->status,
-                                        c->stream));
+                                        finp(c, false), c->stream));
     HIPCHK(c, launch_reduce_only(c->partials, c->nparts, c->reduce_out, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->reduce_host, c->reduce_out, 2 * sizeof(double),
                              hipMemcpyDeviceToHost, c->stream));
@@ -276,9 +286,7 @@ int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
     if (accG) HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<T>(c->g, P::links(c, 0), P::field(c, 0), c->partials, c->status,
-                                   c->stream));
-    HIPCHK(c, launch_finalize(c->partials, c->nparts, c->status, normF(c), normT(c), 0.0, n + 1,
-                              0, c->histF, c->histT, HIST_CAP, c->stream));
+                                   finp(c, true, 0.0, n + 1, 0), c->stream));
     std::vector<hipEvent_t> ev((size_t)n * 6);
     for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
     const T half_alpha = (T)(0.5 * alpha);
@@ -299,10 +307,8 @@ int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
         chk(hipEventRecord(e[3], c->stream));
         chk(launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
                              accG ? c->G32 : nullptr, half_alpha, c->partials, c->status,
-                             c->stream));
+                             finp(c, true, 0.0, n + 1, 1), c->stream));
         chk(hipEventRecord(e[4], c->stream));
-        chk(launch_finalize(c->partials, c->nparts, c->status, normF(c), normT(c), 0.0, n + 1, 1,
-                            c->histF, c->histT, HIST_CAP, c->stream));
         chk(hipEventRecord(e[5], c->stream));
         if (err != hipSuccess) rc = fail(c, LGF_ERR_DEVICE, hipGetErrorString(err));
     }
@@ -335,8 +341,9 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
                     "unsupported lattice extent (allowed: 2 3 4 6 8 12 16 24 32 48 64 96 128)");
     {
         geom g0{L[0], L[1], L[2], L[3], 1};
-        if (fft_zt_lds_bytes<double>(g0, 1) > 160 * 1024)
-            return fail(nullptr, LGF_ERR_ARG, "Lz*Lt too large for one (z,t) tile in LDS");
+        if (plan_zt<double>(g0, ZT_LDS_BUDGET).lds > 160 * 1024 ||
+            fft_xy_lds_bytes<double>(g0) > 160 * 1024)
+            return fail(nullptr, LGF_ERR_ARG, "lattice planes too large for one LDS tile");
     }
     if (precision != LGF_FP64 && precision != LGF_MIXED)
         return fail(nullptr, LGF_ERR_ARG, "precision must be LGF_FP64 or LGF_MIXED");
@@ -372,6 +379,7 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
     ok = ok && alloc((void **)&c->reduce_out, 2 * sizeof(double));
     ok = ok && alloc((void **)&c->histF, HIST_CAP * sizeof(double));
     ok = ok && alloc((void **)&c->histT, HIST_CAP * sizeof(double));
+    ok = ok && alloc((void **)&c->counter, sizeof(unsigned));
     ok = ok && hipHostMalloc((void **)&c->status_host, sizeof(dev_status), 0) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->reduce_host, 2 * sizeof(double), 0) == hipSuccess;
     if (!ok) {
@@ -390,15 +398,16 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
     std::vector<double> pt64(pt.begin(), pt.end());
     std::vector<float> pt32(pt.begin(), pt.end());
     hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemset(c->counter, 0, sizeof(unsigned));
     if (e == hipSuccess) e = hipMemcpy(c->tw64, tw64.data(), TW_M * sizeof(double2), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->tw32, tw32.data(), TW_M * sizeof(float2), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->pt64, pt64.data(), nt * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->pt32, pt32.data(), nt * sizeof(float), hipMemcpyHostToDevice);
-    c->W64 = pick_W<double>(c->g);
-    c->W32 = pick_W<float>(c->g);
+    c->zt64 = plan_zt<double>(c->g, ZT_LDS_BUDGET);
+    c->zt32 = plan_zt<float>(c->g, ZT_LDS_BUDGET);
     // best effort: a launch that still exceeds the limit reports its own error
-    (void)fft_zt_set_max_lds<double>(fft_zt_lds_bytes<double>(c->g, c->W64));
-    (void)fft_zt_set_max_lds<float>(fft_zt_lds_bytes<float>(c->g, c->W32));
+    fft_set_max_lds<double>(c->g, c->zt64);
+    fft_set_max_lds<float>(c->g, c->zt32);
     if (e != hipSuccess) {
         std::string m = std::string("initialisation failed: ") + hipGetErrorString(e);
         lgf_destroy(c);
@@ -415,7 +424,7 @@ void lgf_destroy(lgf_ctx *c) {
     else (void)hipDeviceSynchronize();
     void *dev[] = {c->L64[0], c->L64[1], c->D64[0], c->D64[1], c->G32, c->tw64, c->tw32,
                    c->pt64, c->pt32, c->partials, c->status, c->reduce_out, c->histF, c->histT,
-                   c->gaos, c->Lrot};
+                   c->gaos, c->Lrot, c->counter};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->status_host) (void)hipHostFree(c->status_host);
@@ -583,7 +592,7 @@ int lgf_divergence(lgf_ctx *c, const double *U, double *Delta) {
     HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<double>(c->g, c->L64[0], c->D64[0], c->partials, c->status,
-                                        c->stream));
+                                        finp(c, false), c->stream));
     HIPCHK(c, launch_matrix_from_field(c->D64[0], Delta, c->g.V, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LGF_OK;
@@ -598,7 +607,7 @@ int lgf_fourier_accelerate(lgf_ctx *c, const double *D, double *LD) {
     HIPCHK(c, launch_field_from_matrix(D, c->D64[0], c->g.V, c->stream));
     HIPCHK(c, launch_fft_xy<double>(c->g, c->D64[0], -1, c->tw64, c->status, c->stream));
     HIPCHK(c, launch_fft_zt<double>(c->g, c->D64[0], 0, c->tw64, c->pt64,
-                                    c->p2max / (double)c->g.V, c->W64, c->status, c->stream));
+                                    c->p2max / (double)c->g.V, c->zt64, c->status, c->stream));
     HIPCHK(c, launch_fft_xy<double>(c->g, c->D64[0], +1, c->tw64, c->status, c->stream));
     HIPCHK(c, launch_matrix_from_field(c->D64[0], LD, c->g.V, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -614,14 +623,14 @@ int lgf_fft4d(lgf_ctx *c, double *fields, int sign) {
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     if (sign < 0) {
         HIPCHK(c, launch_fft_xy<double>(c->g, F, -1, c->tw64, c->status, c->stream));
-        HIPCHK(c, launch_fft_zt<double>(c->g, F, -1, c->tw64, c->pt64, 0.0, c->W64, c->status,
+        HIPCHK(c, launch_fft_zt<double>(c->g, F, -1, c->tw64, c->pt64, 0.0, c->zt64, c->status,
                                         c->stream));
         HIPCHK(c, launch_reorder_fields(c->g, F, c->D64[0], 1, c->stream));
     } else {
         HIPCHK(c, launch_reorder_fields(c->g, F, c->D64[0], 0, c->stream));
         HIPCHK(c, hipMemcpyAsync(F, c->D64[0], (size_t)4 * c->g.V * sizeof(double2),
                                  hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, launch_fft_zt<double>(c->g, F, +1, c->tw64, c->pt64, 0.0, c->W64, c->status,
+        HIPCHK(c, launch_fft_zt<double>(c->g, F, +1, c->tw64, c->pt64, 0.0, c->zt64, c->status,
                                         c->stream));
         HIPCHK(c, launch_fft_xy<double>(c->g, F, +1, c->tw64, c->status, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -655,7 +664,7 @@ int lgf_functional_omega_grad(lgf_ctx *c, const double *U, const double *omega, 
     HIPCHK(c, launch_rotate_links(c->g, c->L64[0], c->gaos, c->Lrot, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<double>(c->g, c->Lrot, c->D64[0], c->partials, c->status,
-                                        c->stream));
+                                        finp(c, false), c->stream));
     double A, B;
     rc = sum_partials(c, A, B);
     if (rc) return rc;
@@ -679,7 +688,8 @@ int lgf_theta_grad(lgf_ctx *c, const double *U, const double *eps, double *theta
         Lw = c->Lrot;
     }
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
-    HIPCHK(c, launch_div_reduce<double>(c->g, Lw, c->D64[0], c->partials, c->status, c->stream));
+    HIPCHK(c, launch_div_reduce<double>(c->g, Lw, c->D64[0], c->partials, c->status,
+                                        finp(c, false), c->stream));
     double A, B;
     rc = sum_partials(c, A, B);
     if (rc) return rc;

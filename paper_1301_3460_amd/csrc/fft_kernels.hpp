@@ -1,0 +1,463 @@
+// FFT pass kernels and their launchers, templated on the real type.  The
+// translation units fft_f64.hip and fft_f32.hip instantiate them.
+//
+//   k_fft_xy / k_fft_zt        whole tile in LDS (any supported extent)
+//   k_fft_xy_rc / k_fft_zt_rc  one axis held in registers, the other
+//                              exchanged through LDS in chunks (extents <= 32)
+#pragma once
+#include "common.hpp"
+
+namespace lgf {
+
+static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// (x, y) plane transform: one plane of one field per block, LDS [y][x+1]
+// ---------------------------------------------------------------------------
+
+constexpr int XY_BLOCK = 64;
+
+template <class T, int DIR>
+__global__ void __launch_bounds__(XY_BLOCK)
+    k_fft_xy(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
+             const dev_status *__restrict__ status) {
+    if (status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
+    const int Lx = g.Lx, Ly = g.Ly, P = Lx + 1;
+    const long Lxy = (long)Lx * Ly;
+    vec2_t<T> *plane = D + (long)blockIdx.y * g.V + (long)blockIdx.x * Lxy;
+    for (int i = threadIdx.x; i < Lxy; i += XY_BLOCK) {
+        const int y = i / Lx, x = i - y * Lx;
+        lds[y * P + x] = plane[i];
+    }
+    __syncthreads();
+    auto rows = [P](int c) { return c * P; };
+    auto cols = [](int c) { return c; };
+    if (DIR < 0) {
+        lds_axis_fft<DIR, T>(Lx, lds, Ly, 1, rows, tw);
+        __syncthreads();
+        lds_axis_fft<DIR, T>(Ly, lds, Lx, P, cols, tw);
+    } else {
+        lds_axis_fft<DIR, T>(Ly, lds, Lx, P, cols, tw);
+        __syncthreads();
+        lds_axis_fft<DIR, T>(Lx, lds, Ly, 1, rows, tw);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < Lxy; i += XY_BLOCK) {
+        const int y = i / Lx, x = i - y * Lx;
+        plane[i] = lds[y * P + x];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// (z, t) transform of W consecutive xy-sites of one field per block.
+// LDS element (w, z, t) at t*PT + z*W + w, PT = Lz*W + ZT_PAD.
+// MODE 0: forward z,t; scale by p2max/(V p2); inverse t,z.  -1 / +1: one way.
+// ---------------------------------------------------------------------------
+
+constexpr int ZT_BLOCK = 256;
+constexpr int ZT_PAD = 4;
+
+template <int N, class T, class Base, class Scale>
+__device__ __forceinline__ void t_fwd_scale_inv(vec2_t<T> *lds, int ncols, int stride, Base base,
+                                                Scale scale, const vec2_t<T> *__restrict__ tw) {
+    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+        const int b0 = base(c);
+        cpx<T> a[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) a[j] = ld<T>(lds + b0 + j * stride);
+        dft<N, -1>(a, tw);
+#pragma unroll
+        for (int j = 0; j < N; ++j) a[j] = scale(c, j) * a[j];
+        dft<N, +1>(a, tw);
+#pragma unroll
+        for (int j = 0; j < N; ++j) st<T>(lds + b0 + j * stride, a[j]);
+    }
+}
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(ZT_BLOCK)
+    k_fft_zt(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
+             const T *__restrict__ ptab, T p2max_over_V, int W,
+             const dev_status *__restrict__ status) {
+    if (status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
+    const int Lz = g.Lz, Lt = g.Lt;
+    const long Lxy = (long)g.Lx * g.Ly;
+    const int PT = Lz * W + ZT_PAD;
+    const long s0 = (long)xcd_block(blockIdx.x, gridDim.x) * W;
+    const int Wt = (int)min((long)W, Lxy - s0);
+    vec2_t<T> *F = D + (long)blockIdx.y * g.V;
+    const int nel = W * Lz * Lt;
+    for (int i = threadIdx.x; i < nel; i += ZT_BLOCK) {
+        const int w = i % W, zt = i / W, z = zt % Lz, t = zt / Lz;
+        vec2_t<T> v;
+        v.x = 0;
+        v.y = 0;
+        if (w < Wt) v = F[(long)zt * Lxy + s0 + w];
+        lds[t * PT + z * W + w] = v;
+    }
+    __syncthreads();
+    auto zcol = [W, PT](int c) { return (c / W) * PT + (c % W); };  // c = w + W*t
+    auto tcol = [W](int c) { return c; };                          // c = w + W*z
+    if (MODE <= 0) {
+        lds_axis_fft<-1, T>(Lz, lds, W * Lt, W, zcol, tw);
+        __syncthreads();
+    }
+    if (MODE == 0) {
+        const T *px = ptab, *py = ptab + g.Lx, *pz = ptab + g.Lx + g.Ly,
+                *pt = ptab + g.Lx + g.Ly + g.Lz;
+        const int Lx = g.Lx;
+        auto scale = [=](int c, int j) -> T {
+            const int w = c % W, z = c / W;
+            const long sxy = s0 + w;
+            if (sxy >= Lxy) return T(0);  // padding column of a ragged tile
+            const int x = (int)(sxy % Lx), y = (int)(sxy / Lx);
+            const T p2 = (px[x] + py[y]) + (pz[z] + pt[j]);
+            return p2 == T(0) ? T(0) : p2max_over_V / p2;
+        };
+        switch (Lt) {
+#define LGF_TCASE(NN) \
+    case NN: t_fwd_scale_inv<NN, T>(lds, W * Lz, PT, tcol, scale, tw); break;
+            LGF_TCASE(2) LGF_TCASE(3) LGF_TCASE(4) LGF_TCASE(6) LGF_TCASE(8) LGF_TCASE(12)
+            LGF_TCASE(16) LGF_TCASE(24) LGF_TCASE(32)
+#undef LGF_TCASE
+        default: {
+            lds_axis_fft<-1, T>(Lt, lds, W * Lz, PT, tcol, tw);
+            __syncthreads();
+            for (int i = threadIdx.x; i < W * Lz * Lt; i += ZT_BLOCK) {
+                const int c = i % (W * Lz), j = i / (W * Lz);
+                vec2_t<T> *p = lds + j * PT + c;
+                const T f = scale(c, j);
+                vec2_t<T> v = *p;
+                v.x *= f;
+                v.y *= f;
+                *p = v;
+            }
+            __syncthreads();
+            lds_axis_fft<+1, T>(Lt, lds, W * Lz, PT, tcol, tw);
+        } break;
+        }
+        __syncthreads();
+    } else {
+        lds_axis_fft<MODE, T>(Lt, lds, W * Lz, PT, tcol, tw);
+        __syncthreads();
+    }
+    if (MODE >= 0) {
+        lds_axis_fft<+1, T>(Lz, lds, W * Lt, W, zcol, tw);
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < nel; i += ZT_BLOCK) {
+        const int w = i % W, zt = i / W, z = zt % Lz, t = zt / Lz;
+        if (w < Wt) F[(long)zt * Lxy + s0 + w] = lds[t * PT + z * W + w];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Register-column transforms (register-axis extent up to 32).
+//
+// Each thread keeps the whole column of one strided lattice axis (t for the
+// (z,t) pass, y for the (x,y) pass) in registers, loaded straight from HBM so
+// that consecutive lanes read consecutive sites.  The other axis is
+// transformed through LDS in chunks of a few register positions: every thread
+// writes its chunk, the columns of the exchanged axis are transformed, and the
+// values are read back.  LDS element (w, b, j) of a chunk is at
+// j*PJ + b*SB + w*SW.
+// ---------------------------------------------------------------------------
+
+__host__ __device__ constexpr int rc_chunk(int na) {
+    return na % 8 == 0 ? 8 : na % 6 == 0 ? 6 : na % 4 == 0 ? 4 : na % 3 == 0 ? 3 : na;
+}
+
+// The chunk loop stays rolled: the chunk in flight is always a[0..C), and the
+// register array is rotated left by C after each chunk (NA/C rotations bring
+// it back to its original order), so every register index is static.
+template <int NA, class T, class ColFn>
+__device__ __forceinline__ void exchange_axis(cpx<T> (&a)[NA], int w, int b, int SB, int SW,
+                                              int PJ, vec2_t<T> *lds, ColFn col) {
+    constexpr int C = rc_chunk(NA);
+    vec2_t<T> *mine = lds + b * SB + w * SW;
+#pragma unroll 1
+    for (int c0 = 0; c0 < NA; c0 += C) {
+#pragma unroll
+        for (int j = 0; j < C; ++j) st<T>(mine + j * PJ, a[j]);
+        __syncthreads();
+        col(c0, C);
+        __syncthreads();
+        cpx<T> head[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) head[j] = ld<T>(mine + j * PJ);
+#pragma unroll
+        for (int i = 0; i < NA - C; ++i) a[i] = a[i + C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) a[NA - C + j] = head[j];
+        __syncthreads();
+    }
+}
+
+// Column transform forward, times scale(c, position), inverse: one register
+// pass when the extent is at most 32, else three LDS passes.
+template <int N, class T, class Base, class Scale>
+__device__ __forceinline__ void col_fwd_scale_inv_n(vec2_t<T> *lds, int ncols, int stride, Base base,
+                                                    Scale scale, const vec2_t<T> *__restrict__ tw) {
+    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+        const int b0 = base(c);
+        cpx<T> v[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = ld<T>(lds + b0 + k * stride);
+        dft<N, -1>(v, tw);
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = scale(c, k) * v[k];
+        dft<N, +1>(v, tw);
+#pragma unroll
+        for (int k = 0; k < N; ++k) st<T>(lds + b0 + k * stride, v[k]);
+    }
+}
+
+template <class T, class Base, class Scale>
+__device__ __forceinline__ void col_fwd_scale_inv(int n, vec2_t<T> *lds, int ncols, int stride,
+                                                  Base base, Scale scale,
+                                                  const vec2_t<T> *__restrict__ tw) {
+    switch (n) {
+#define LGF_SCASE(NN) \
+    case NN: col_fwd_scale_inv_n<NN, T>(lds, ncols, stride, base, scale, tw); break;
+        LGF_SCASE(2) LGF_SCASE(3) LGF_SCASE(4) LGF_SCASE(6) LGF_SCASE(8) LGF_SCASE(12)
+        LGF_SCASE(16) LGF_SCASE(24) LGF_SCASE(32)
+#undef LGF_SCASE
+    default: break;
+    }
+}
+
+// One-pass column transform of an extent up to 32.
+template <int DIR, class T, class Base>
+__device__ __forceinline__ void col_fft_small(int n, vec2_t<T> *lds, int ncols, int stride,
+                                              Base base, const vec2_t<T> *__restrict__ tw) {
+    switch (n) {
+#define LGF_CCASE(NN) \
+    case NN: lds_axis_fft_n<NN, DIR, T>(lds, ncols, stride, base, tw); break;
+        LGF_CCASE(2) LGF_CCASE(3) LGF_CCASE(4) LGF_CCASE(6) LGF_CCASE(8) LGF_CCASE(12)
+        LGF_CCASE(16) LGF_CCASE(24) LGF_CCASE(32)
+#undef LGF_CCASE
+    default: break;
+    }
+}
+
+template <class T> constexpr int rc_max_threads() { return sizeof(T) == 8 ? 256 : 512; }
+
+// (x, y) pass: F fields of one plane per block, thread (f, x) holds a y-column.
+template <class T, int NY, int DIR>
+__global__ void __launch_bounds__(rc_max_threads<T>())
+    k_fft_xy_rc(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw, int F,
+                const dev_status *__restrict__ status) {
+    if (status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
+    const int Lx = g.Lx;
+    const long Lxy = (long)Lx * NY;
+    const int x = threadIdx.x % Lx, fl = threadIdx.x / Lx;
+    const int f = blockIdx.y * F + fl;
+    const int SW = Lx + 1, PJ = F * SW;
+    vec2_t<T> *p = D + (long)f * g.V + (long)blockIdx.x * Lxy + x;
+    cpx<T> a[NY];
+#pragma unroll
+    for (int y = 0; y < NY; ++y) a[y] = ld<T>(p + (long)y * Lx);
+    auto base = [F, SW, PJ](int c) { return (c / F) * PJ + (c % F) * SW; };  // c = fl + F*j
+    auto col = [&](int, int C) { col_fft_small<DIR, T>(Lx, lds, F * C, 1, base, tw); };
+    if (DIR < 0) {
+        dft<NY, -1>(a, tw);
+        exchange_axis<NY, T>(a, fl, x, 1, SW, PJ, lds, col);
+    } else {
+        exchange_axis<NY, T>(a, fl, x, 1, SW, PJ, lds, col);
+        dft<NY, +1>(a, tw);
+    }
+#pragma unroll
+    for (int y = 0; y < NY; ++y) st<T>(p + (long)y * Lx, a[y]);
+}
+
+// (z, t) pass: W consecutive xy-sites of one field per block, thread (w, z)
+// holds a t-column.  MODE 0: forward, scale by p2max/(V p2), inverse.
+template <class T, int NT, int MODE>
+__global__ void __launch_bounds__(rc_max_threads<T>())
+    k_fft_zt_rc(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
+                const T *__restrict__ ptab, T p2max_over_V, int W,
+                const dev_status *__restrict__ status) {
+    if (status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
+    const int Lz = g.Lz;
+    const long Lxy = (long)g.Lx * g.Ly;
+    const int w = threadIdx.x % W, z = threadIdx.x / W;
+    const long s0 = (long)xcd_block(blockIdx.x, gridDim.x) * W;
+    const bool live = s0 + w < Lxy;
+    vec2_t<T> *p = D + (long)blockIdx.y * g.V + (long)z * Lxy + s0 + w;
+    const long tstride = (long)Lz * Lxy;
+    cpx<T> a[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) a[t] = live ? ld<T>(p + t * tstride) : mk<T>(0, 0);
+    const int PJ = Lz * W + ZT_PAD;
+    auto base = [W, PJ](int c) { return (c / W) * PJ + (c % W); };  // c = w + W*j
+    if (MODE <= 0) dft<NT, -1>(a, tw);
+    if (MODE == 0) {
+        const T *px = ptab, *py = ptab + g.Lx, *pz = ptab + g.Lx + g.Ly,
+                *pt = ptab + g.Lx + g.Ly + g.Lz;
+        const int Lx = g.Lx;
+        auto col = [&](int c0, int C) {
+            auto scale = [=](int c, int k) -> T {
+                const long sxy = s0 + (c % W);
+                if (sxy >= Lxy) return T(0);  // padding column of a ragged tile
+                const int x = (int)(sxy % Lx), y = (int)(sxy / Lx);
+                const T p2 = (px[x] + py[y]) + (pz[k] + pt[c0 + c / W]);
+                return p2 == T(0) ? T(0) : p2max_over_V / p2;
+            };
+            col_fwd_scale_inv<T>(Lz, lds, W * C, W, base, scale, tw);
+        };
+        exchange_axis<NT, T>(a, w, z, W, 1, PJ, lds, col);
+    } else {
+        auto col = [&](int, int C) { col_fft_small<MODE, T>(Lz, lds, W * C, W, base, tw); };
+        exchange_axis<NT, T>(a, w, z, W, 1, PJ, lds, col);
+    }
+    if (MODE >= 0) dft<NT, +1>(a, tw);
+    if (live) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) st<T>(p + t * tstride, a[t]);
+    }
+}
+
+#define LGF_NA_CASES(MACRO)                                                        \
+    MACRO(2) MACRO(3) MACRO(4) MACRO(6) MACRO(8) MACRO(12) MACRO(16) MACRO(24) MACRO(32)
+
+template <class T> inline int xy_fields_per_block(const geom &g) {
+    int F = 4;
+    while (F > 1 && F * g.Lx > rc_max_threads<T>()) F >>= 1;
+    return F;
+}
+
+template <class T> inline bool xy_use_rc(const geom &g) { return g.Ly <= 32 && g.Lx <= 32; }
+
+template <class T> size_t fft_xy_lds_bytes(const geom &g) {
+    if (xy_use_rc<T>(g))
+        return (size_t)rc_chunk(g.Ly) * xy_fields_per_block<T>(g) * (g.Lx + 1) * sizeof(vec2_t<T>);
+    return (size_t)g.Ly * (g.Lx + 1) * sizeof(vec2_t<T>);
+}
+
+template <class T>
+hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const dev_status *status,
+                         hipStream_t st) {
+    auto Dp = static_cast<vec2_t<T> *>(D);
+    auto twp = static_cast<const vec2_t<T> *>(tw);
+    const size_t lds = fft_xy_lds_bytes<T>(g);
+    if (xy_use_rc<T>(g)) {
+        const int F = xy_fields_per_block<T>(g);
+        dim3 grid((unsigned)(g.Lz * g.Lt), 4 / F);
+        const unsigned nt = (unsigned)(F * g.Lx);
+#define LGF_XY(NN)                                                                            \
+    case NN:                                                                                  \
+        if (dir < 0) k_fft_xy_rc<T, NN, -1><<<grid, nt, lds, st>>>(g, Dp, twp, F, status);   \
+        else k_fft_xy_rc<T, NN, 1><<<grid, nt, lds, st>>>(g, Dp, twp, F, status);            \
+        break;
+        switch (g.Ly) {
+            LGF_NA_CASES(LGF_XY)
+        default: return hipErrorInvalidValue;
+        }
+#undef LGF_XY
+        return hipGetLastError();
+    }
+    dim3 grid((unsigned)(g.Lz * g.Lt), 4);
+    if (dir < 0) k_fft_xy<T, -1><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
+    else k_fft_xy<T, +1><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
+    return hipGetLastError();
+}
+
+// (z,t) plan: register-column kernel when Lt <= 32 (tile of W sites with
+// 128-byte rows), else the LDS-tile kernel with the widest W that fits.
+template <class T> zt_plan plan_zt(const geom &g, size_t lds_budget) {
+    zt_plan p{};
+    const long Lxy = (long)g.Lx * g.Ly;
+    if (g.Lt <= 32 && g.Lz <= 32) {
+        int W = 128 / (int)sizeof(vec2_t<T>);
+        while (W > 1 && (W * g.Lz > rc_max_threads<T>() || W > Lxy)) W >>= 1;
+        if (W * g.Lz <= rc_max_threads<T>()) {
+            p.rc = true;
+            p.W = W;
+            p.lds = (size_t)rc_chunk(g.Lt) * ((size_t)g.Lz * W + ZT_PAD) * sizeof(vec2_t<T>);
+            return p;
+        }
+    }
+    int W = 16;
+    auto bytes = [&](int w) { return (size_t)g.Lt * ((size_t)g.Lz * w + ZT_PAD) * sizeof(vec2_t<T>); };
+    while (W > 1 && ((long)W > Lxy || bytes(W) > lds_budget)) W >>= 1;
+    p.rc = false;
+    p.W = W;
+    p.lds = bytes(W);
+    return p;
+}
+
+template <class T> void fft_set_max_lds(const geom &g, const zt_plan &p) {
+    auto set = [](const void *f, size_t b) {
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+    };
+    if (p.rc) {
+#define LGF_ZTA(NN)                                                                 \
+    case NN:                                                                        \
+        set(reinterpret_cast<const void *>(&k_fft_zt_rc<T, NN, 0>), p.lds);        \
+        set(reinterpret_cast<const void *>(&k_fft_zt_rc<T, NN, -1>), p.lds);       \
+        set(reinterpret_cast<const void *>(&k_fft_zt_rc<T, NN, 1>), p.lds);        \
+        break;
+        switch (g.Lt) {
+            LGF_NA_CASES(LGF_ZTA)
+        default: break;
+        }
+#undef LGF_ZTA
+    } else {
+        set(reinterpret_cast<const void *>(&k_fft_zt<T, 0>), p.lds);
+        set(reinterpret_cast<const void *>(&k_fft_zt<T, -1>), p.lds);
+        set(reinterpret_cast<const void *>(&k_fft_zt<T, 1>), p.lds);
+    }
+    if (!xy_use_rc<T>(g)) {
+        set(reinterpret_cast<const void *>(&k_fft_xy<T, -1>), fft_xy_lds_bytes<T>(g));
+        set(reinterpret_cast<const void *>(&k_fft_xy<T, 1>), fft_xy_lds_bytes<T>(g));
+    }
+}
+
+template <class T>
+hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const T *ptab,
+                         T p2max_over_V, const zt_plan &pl, const dev_status *status,
+                         hipStream_t st) {
+    const long Lxy = (long)g.Lx * g.Ly;
+    const int W = pl.W;
+    dim3 grid((unsigned)((Lxy + W - 1) / W), 4);
+    auto Dp = static_cast<vec2_t<T> *>(D);
+    auto twp = static_cast<const vec2_t<T> *>(tw);
+    if (pl.rc) {
+        const unsigned nt = (unsigned)(W * g.Lz);
+#define LGF_ZT(NN)                                                                                \
+    case NN:                                                                                      \
+        if (mode == 0)                                                                            \
+            k_fft_zt_rc<T, NN, 0><<<grid, nt, pl.lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W,   \
+                                                            status);                              \
+        else if (mode < 0)                                                                        \
+            k_fft_zt_rc<T, NN, -1><<<grid, nt, pl.lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W,  \
+                                                             status);                             \
+        else                                                                                      \
+            k_fft_zt_rc<T, NN, 1><<<grid, nt, pl.lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W,   \
+                                                            status);                              \
+        break;
+        switch (g.Lt) {
+            LGF_NA_CASES(LGF_ZT)
+        default: return hipErrorInvalidValue;
+        }
+#undef LGF_ZT
+        return hipGetLastError();
+    }
+    if (mode == 0)
+        k_fft_zt<T, 0><<<grid, ZT_BLOCK, pl.lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W, status);
+    else if (mode < 0)
+        k_fft_zt<T, -1><<<grid, ZT_BLOCK, pl.lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W, status);
+    else
+        k_fft_zt<T, 1><<<grid, ZT_BLOCK, pl.lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W, status);
+    return hipGetLastError();
+}
+
+}  // namespace lgf

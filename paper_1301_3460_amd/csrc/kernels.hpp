@@ -20,6 +20,16 @@ struct dev_status {
 enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXITER = 4, ST_NONFINITE = 5, ST_DIVERGING = 6 };
 constexpr int DIVERGE_RISES = 8;
 
+// Stopping test run by the last block of a sweep kernel to finish (it sums
+// the per-block partials in fixed order, so the result does not depend on
+// which block that is).  enabled == 0: partials only.
+struct fin_params {
+    double normF, normT, tol;
+    int max_iter, increment, hist_cap, enabled;
+    double *histF, *histT;
+    unsigned *counter;  // zero between launches; reset by the last block
+};
+
 struct geom {
     int Lx, Ly, Lz, Lt;
     long V;
@@ -35,30 +45,39 @@ hipError_t launch_unpack_links(const void *L64, double *Uaos, long V, hipStream_
 
 template <class T>
 hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *partials,
-                             const dev_status *status, hipStream_t st);
+                             dev_status *status, const fin_params &fp, hipStream_t st);
 
 template <class T>
 hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void *LD, void *Dout,
-                         void *G, T c, double *partials, const dev_status *status, hipStream_t st);
+                         void *G, T c, double *partials, dev_status *status,
+                         const fin_params &fp, hipStream_t st);
 
 // mode: -1 forward only, +1 inverse only (x,y pass: direction)
 template <class T>
 hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw,
                          const dev_status *status, hipStream_t st);
+// (z,t) pass plan: register-column kernel (rc) or LDS-tile kernel, tile width
+// W (consecutive xy-sites per block) and dynamic LDS bytes.
+struct zt_plan {
+    bool rc;
+    int W;
+    size_t lds;
+};
+template <class T> zt_plan plan_zt(const geom &g, size_t lds_budget);
+template <class T> size_t fft_xy_lds_bytes(const geom &g);
+template <class T> void fft_set_max_lds(const geom &g, const zt_plan &p);
 // mode 0: forward, scale by p2max/(V p2), inverse; -1: forward only; +1: inverse only
 template <class T>
 hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const T *ptab,
-                         T p2max_over_V, int W, const dev_status *status, hipStream_t st);
-template <class T> size_t fft_zt_lds_bytes(const geom &g, int W);
-template <class T> hipError_t fft_zt_set_max_lds(size_t bytes);
+                         T p2max_over_V, const zt_plan &pl, const dev_status *status,
+                         hipStream_t st);
 
 // natural <-> transform-position order of 4 fields (dir -1: positions -> natural)
 hipError_t launch_reorder_fields(const geom &g, const double2 *in, double2 *out, int to_natural,
                                  hipStream_t st);
 
-hipError_t launch_finalize(const double *partials, int nparts, dev_status *status, double normF,
-                           double normT, double tol, int max_iter, int increment, double *histF,
-                           double *histT, int hist_cap, hipStream_t st);
+hipError_t launch_finalize(const double *partials, int nparts, dev_status *status,
+                           const fin_params &fp, hipStream_t st);
 hipError_t launch_status_reset(dev_status *status, int hist_base, hipStream_t st);
 hipError_t launch_reduce_only(const double *partials, int nparts, double *out2, hipStream_t st);
 

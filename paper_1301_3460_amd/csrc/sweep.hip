@@ -12,73 +12,9 @@
 //   finalize    fixed-order sum of the partials, stopping test
 // Links are double-buffered (the update reads U_mu(x-mu) of other threads),
 // as are the Fourier fields.
-#include "fft.hpp"
-#include "kernels.hpp"
-#include "su3.hpp"
+#include "common.hpp"
 
 namespace lgf {
-
-// ---------------------------------------------------------------------------
-// helpers
-// ---------------------------------------------------------------------------
-
-// Blocks are dispatched round-robin over the 8 XCDs; map them so that each
-// XCD (own L2) walks a contiguous range of sites and neighbour data is shared.
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-    const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
-    return x * q + (x < r ? x : r) + k;
-}
-
-struct nbr {
-    long p[4], m[4];  // s + mu, s - mu (periodic)
-};
-
-__device__ __forceinline__ nbr neighbours(const geom &g, long s) {
-    nbr n;
-    long r = s;
-    const int x = (int)(r % g.Lx); r /= g.Lx;
-    const int y = (int)(r % g.Ly); r /= g.Ly;
-    const int z = (int)(r % g.Lz);
-    const int t = (int)(r / g.Lz);
-    const long sy = g.Lx, sz = (long)g.Lx * g.Ly, stt = sz * g.Lz;
-    n.p[0] = (x == g.Lx - 1) ? s - (g.Lx - 1) : s + 1;
-    n.m[0] = (x == 0) ? s + (g.Lx - 1) : s - 1;
-    n.p[1] = (y == g.Ly - 1) ? s - (long)(g.Ly - 1) * sy : s + sy;
-    n.m[1] = (y == 0) ? s + (long)(g.Ly - 1) * sy : s - sy;
-    n.p[2] = (z == g.Lz - 1) ? s - (long)(g.Lz - 1) * sz : s + sz;
-    n.m[2] = (z == 0) ? s + (long)(g.Lz - 1) * sz : s - sz;
-    n.p[3] = (t == g.Lt - 1) ? s - (long)(g.Lt - 1) * stt : s + stt;
-    n.m[3] = (t == 0) ? s + (long)(g.Lt - 1) * stt : s - stt;
-    return n;
-}
-
-// Deterministic block sum of two doubles into partials[2*slot + {0,1}].
-template <int NT>
-__device__ __forceinline__ void block_sum2(double a, double b, double *partials, int slot) {
-    static_assert(NT % 64 == 0, "wave64 blocks");
-    __shared__ double sa[NT / 64], sb[NT / 64];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off);
-        b += __shfl_xor(b, off);
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        sa[w] = a;
-        sb[w] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double A = 0, B = 0;
-#pragma unroll
-        for (int i = 0; i < NT / 64; ++i) {
-            A += sa[i];
-            B += sb[i];
-        }
-        partials[2 * slot] = A;
-        partials[2 * slot + 1] = B;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // layout conversion
@@ -143,13 +79,99 @@ __global__ void k_matrix_from_field(const double2 *__restrict__ D, double2 *__re
 }
 
 // ---------------------------------------------------------------------------
+// finalize: fixed-order sum of block partials and the stopping test
+// ---------------------------------------------------------------------------
+
+constexpr int FIN_BLOCK = 256;
+
+template <int NT>
+__device__ __forceinline__ void fixed_order_sum(const volatile double *partials, int nparts,
+                                                double &A, double &B) {
+    double a = 0, b = 0;
+    for (int i = threadIdx.x; i < nparts; i += NT) {
+        a += partials[2 * i];
+        b += partials[2 * i + 1];
+    }
+    __shared__ double sa[NT], sb[NT];
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sa[threadIdx.x] += sa[threadIdx.x + h];
+            sb[threadIdx.x] += sb[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    A = sa[0];
+    B = sb[0];
+}
+
+// F = A normF, theta = B normT; history, stopping test (one thread)
+__device__ __forceinline__ void finalize_state(double A, double B, dev_status *status,
+                                               const fin_params &fp) {
+    const double F = A * fp.normF, th = B * fp.normT;
+    dev_status st = *status;
+    if (fp.increment) st.n += 1;
+    const int h = st.hist_base + st.n;
+    if (h < fp.hist_cap) {
+        fp.histF[h] = F;
+        fp.histT[h] = th;
+    }
+    st.F = F;
+    st.theta = th;
+    if (!isfinite(th) || !isfinite(F)) {
+        st.done = 1;
+        st.code = ST_NONFINITE;
+    } else if (th < fp.tol) {
+        st.done = 1;
+        st.code = ST_CONVERGED;
+    } else if (st.n >= fp.max_iter) {
+        st.done = 1;
+        st.code = ST_MAXITER;
+    } else {
+        st.rises = (st.n > 0 && th > st.theta_prev) ? st.rises + 1 : 0;
+        if (st.rises >= DIVERGE_RISES) {
+            st.done = 1;
+            st.code = ST_DIVERGING;
+        }
+    }
+    st.theta_prev = th;
+    *status = st;
+}
+
+// Called by every block after its partial is written: the last block to
+// arrive sums all partials (fixed order) and runs the stopping test.
+template <int NT>
+__device__ __forceinline__ void last_block_finalize(double *partials, int nparts,
+                                                    dev_status *status, const fin_params &fp) {
+    if (!fp.enabled) return;
+    __shared__ int am_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(fp.counter, 1u);
+        am_last = (prev == (unsigned)nparts - 1);
+    }
+    __syncthreads();
+    if (!am_last) return;
+    __threadfence();
+    double A, B;
+    fixed_order_sum<NT>(partials, nparts, A, B);
+    if (threadIdx.x == 0) {
+        finalize_state(A, B, status, fp);
+        atomicExch(fp.counter, 0u);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // divergence and reductions of given links (first sweep of a solve)
 // ---------------------------------------------------------------------------
 
 template <class T>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_div_reduce(geom g, const vec2_t<T> *__restrict__ L, vec2_t<T> *__restrict__ D,
-                 double *__restrict__ partials, const dev_status *__restrict__ status) {
+                 double *__restrict__ partials, dev_status *__restrict__ status, fin_params fp) {
     if (status->done) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const long s = (long)b * SITE_BLOCK + threadIdx.x;
@@ -176,6 +198,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         st<T>(D + 3 * g.V + s, f3);
     }
     block_sum2<SITE_BLOCK>(fs, ts, partials, b);
+    last_block_finalize<SITE_BLOCK>(partials, gridDim.x, status, fp);
 }
 
 // ---------------------------------------------------------------------------
@@ -187,7 +210,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
     k_update(geom g, const vec2_t<T> *__restrict__ Lin, vec2_t<T> *__restrict__ Lout,
              const vec2_t<T> *__restrict__ LD, vec2_t<T> *__restrict__ Dout,
              vec2_t<T> *__restrict__ G, T c, double *__restrict__ partials,
-             const dev_status *__restrict__ status) {
+             dev_status *__restrict__ status, fin_params fp) {
     if (status->done) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const long s = (long)b * SITE_BLOCK + threadIdx.x;
@@ -236,150 +259,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         }
     }
     block_sum2<SITE_BLOCK>(fs, ts, partials, b);
-}
-
-// ---------------------------------------------------------------------------
-// (x, y) plane transform: one plane of one field per block, LDS [y][x+1]
-// ---------------------------------------------------------------------------
-
-constexpr int XY_BLOCK = 64;
-
-template <class T, int DIR>
-__global__ void __launch_bounds__(XY_BLOCK)
-    k_fft_xy(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
-             const dev_status *__restrict__ status) {
-    if (status->done) return;
-    extern __shared__ unsigned char smem_raw[];
-    vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
-    const int Lx = g.Lx, Ly = g.Ly, P = Lx + 1;
-    const long Lxy = (long)Lx * Ly;
-    vec2_t<T> *plane = D + (long)blockIdx.y * g.V + (long)blockIdx.x * Lxy;
-    for (int i = threadIdx.x; i < Lxy; i += XY_BLOCK) {
-        const int y = i / Lx, x = i - y * Lx;
-        lds[y * P + x] = plane[i];
-    }
-    __syncthreads();
-    auto rows = [P](int c) { return c * P; };
-    auto cols = [](int c) { return c; };
-    if (DIR < 0) {
-        lds_axis_fft<DIR, T>(Lx, lds, Ly, 1, rows, tw);
-        __syncthreads();
-        lds_axis_fft<DIR, T>(Ly, lds, Lx, P, cols, tw);
-    } else {
-        lds_axis_fft<DIR, T>(Ly, lds, Lx, P, cols, tw);
-        __syncthreads();
-        lds_axis_fft<DIR, T>(Lx, lds, Ly, 1, rows, tw);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < Lxy; i += XY_BLOCK) {
-        const int y = i / Lx, x = i - y * Lx;
-        plane[i] = lds[y * P + x];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// (z, t) transform of W consecutive xy-sites of one field per block.
-// LDS element (w, z, t) at t*PT + z*W + w, PT = Lz*W + ZT_PAD.
-// MODE 0: forward z,t; scale by p2max/(V p2); inverse t,z.  -1 / +1: one way.
-// ---------------------------------------------------------------------------
-
-constexpr int ZT_BLOCK = 256;
-constexpr int ZT_PAD = 4;
-
-template <int N, class T, class Base, class Scale>
-__device__ __forceinline__ void t_fwd_scale_inv(vec2_t<T> *lds, int ncols, int stride, Base base,
-                                                Scale scale, const vec2_t<T> *__restrict__ tw) {
-    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
-        const int b0 = base(c);
-        cpx<T> a[N];
-#pragma unroll
-        for (int j = 0; j < N; ++j) a[j] = ld<T>(lds + b0 + j * stride);
-        dft<N, -1>(a, tw);
-#pragma unroll
-        for (int j = 0; j < N; ++j) a[j] = scale(c, j) * a[j];
-        dft<N, +1>(a, tw);
-#pragma unroll
-        for (int j = 0; j < N; ++j) st<T>(lds + b0 + j * stride, a[j]);
-    }
-}
-
-template <class T, int MODE>
-__global__ void __launch_bounds__(ZT_BLOCK)
-    k_fft_zt(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
-             const T *__restrict__ ptab, T p2max_over_V, int W,
-             const dev_status *__restrict__ status) {
-    if (status->done) return;
-    extern __shared__ unsigned char smem_raw[];
-    vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
-    const int Lz = g.Lz, Lt = g.Lt;
-    const long Lxy = (long)g.Lx * g.Ly;
-    const int PT = Lz * W + ZT_PAD;
-    const long s0 = (long)xcd_block(blockIdx.x, gridDim.x) * W;
-    const int Wt = (int)min((long)W, Lxy - s0);
-    vec2_t<T> *F = D + (long)blockIdx.y * g.V;
-    const int nel = W * Lz * Lt;
-    for (int i = threadIdx.x; i < nel; i += ZT_BLOCK) {
-        const int w = i % W, zt = i / W, z = zt % Lz, t = zt / Lz;
-        vec2_t<T> v;
-        v.x = 0;
-        v.y = 0;
-        if (w < Wt) v = F[(long)zt * Lxy + s0 + w];
-        lds[t * PT + z * W + w] = v;
-    }
-    __syncthreads();
-    auto zcol = [W, PT](int c) { return (c / W) * PT + (c % W); };  // c = w + W*t
-    auto tcol = [W](int c) { return c; };                          // c = w + W*z
-    if (MODE <= 0) {
-        lds_axis_fft<-1, T>(Lz, lds, W * Lt, W, zcol, tw);
-        __syncthreads();
-    }
-    if (MODE == 0) {
-        const T *px = ptab, *py = ptab + g.Lx, *pz = ptab + g.Lx + g.Ly,
-                *pt = ptab + g.Lx + g.Ly + g.Lz;
-        const int Lx = g.Lx;
-        auto scale = [=](int c, int j) -> T {
-            const int w = c % W, z = c / W;
-            const long sxy = s0 + w;
-            if (sxy >= Lxy) return T(0);  // padding column of a ragged tile
-            const int x = (int)(sxy % Lx), y = (int)(sxy / Lx);
-            const T p2 = (px[x] + py[y]) + (pz[z] + pt[j]);
-            return p2 == T(0) ? T(0) : p2max_over_V / p2;
-        };
-        switch (Lt) {
-#define LGF_TCASE(NN) \
-    case NN: t_fwd_scale_inv<NN, T>(lds, W * Lz, PT, tcol, scale, tw); break;
-            LGF_TCASE(2) LGF_TCASE(3) LGF_TCASE(4) LGF_TCASE(6) LGF_TCASE(8) LGF_TCASE(12)
-            LGF_TCASE(16) LGF_TCASE(24) LGF_TCASE(32)
-#undef LGF_TCASE
-        default: {
-            lds_axis_fft<-1, T>(Lt, lds, W * Lz, PT, tcol, tw);
-            __syncthreads();
-            for (int i = threadIdx.x; i < W * Lz * Lt; i += ZT_BLOCK) {
-                const int c = i % (W * Lz), j = i / (W * Lz);
-                vec2_t<T> *p = lds + j * PT + c;
-                const T f = scale(c, j);
-                vec2_t<T> v = *p;
-                v.x *= f;
-                v.y *= f;
-                *p = v;
-            }
-            __syncthreads();
-            lds_axis_fft<+1, T>(Lt, lds, W * Lz, PT, tcol, tw);
-        } break;
-        }
-        __syncthreads();
-    } else {
-        lds_axis_fft<MODE, T>(Lt, lds, W * Lz, PT, tcol, tw);
-        __syncthreads();
-    }
-    if (MODE >= 0) {
-        lds_axis_fft<+1, T>(Lz, lds, W * Lt, W, zcol, tw);
-        __syncthreads();
-    }
-    for (int i = threadIdx.x; i < nel; i += ZT_BLOCK) {
-        const int w = i % W, zt = i / W, z = zt % Lz, t = zt / Lz;
-        if (w < Wt) F[(long)zt * Lxy + s0 + w] = lds[t * PT + z * W + w];
-    }
+    last_block_finalize<SITE_BLOCK>(partials, gridDim.x, status, fp);
 }
 
 // reorder 4 fields between natural index order and transform-position order
@@ -402,70 +282,13 @@ __global__ void k_reorder(geom g, const double2 *__restrict__ in, double2 *__res
     }
 }
 
-// ---------------------------------------------------------------------------
-// finalize: fixed-order sum of block partials and the stopping test
-// ---------------------------------------------------------------------------
-
-constexpr int FIN_BLOCK = 256;
-
-__device__ __forceinline__ void fixed_order_sum(const double *__restrict__ partials, int nparts,
-                                                double &A, double &B) {
-    double a = 0, b = 0;
-    for (int i = threadIdx.x; i < nparts; i += FIN_BLOCK) {
-        a += partials[2 * i];
-        b += partials[2 * i + 1];
-    }
-    __shared__ double sa[FIN_BLOCK], sb[FIN_BLOCK];
-    sa[threadIdx.x] = a;
-    sb[threadIdx.x] = b;
-    __syncthreads();
-    for (int h = FIN_BLOCK / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
-            sa[threadIdx.x] += sa[threadIdx.x + h];
-            sb[threadIdx.x] += sb[threadIdx.x + h];
-        }
-        __syncthreads();
-    }
-    A = sa[0];
-    B = sb[0];
-}
-
 __global__ void __launch_bounds__(FIN_BLOCK)
     k_finalize(const double *__restrict__ partials, int nparts, dev_status *__restrict__ status,
-               double normF, double normT, double tol, int max_iter, int increment,
-               double *__restrict__ histF, double *__restrict__ histT, int hist_cap) {
+               fin_params fp) {
     if (status->done) return;
     double A, B;
-    fixed_order_sum(partials, nparts, A, B);
-    if (threadIdx.x != 0) return;
-    const double F = A * normF, th = B * normT;
-    dev_status st = *status;
-    if (increment) st.n += 1;
-    const int h = st.hist_base + st.n;
-    if (h < hist_cap) {
-        histF[h] = F;
-        histT[h] = th;
-    }
-    st.F = F;
-    st.theta = th;
-    if (!isfinite(th) || !isfinite(F)) {
-        st.done = 1;
-        st.code = ST_NONFINITE;
-    } else if (th < tol) {
-        st.done = 1;
-        st.code = ST_CONVERGED;
-    } else if (st.n >= max_iter) {
-        st.done = 1;
-        st.code = ST_MAXITER;
-    } else {
-        st.rises = (st.n > 0 && th > st.theta_prev) ? st.rises + 1 : 0;
-        if (st.rises >= DIVERGE_RISES) {
-            st.done = 1;
-            st.code = ST_DIVERGING;
-        }
-    }
-    st.theta_prev = th;
-    *status = st;
+    fixed_order_sum<FIN_BLOCK>(partials, nparts, A, B);
+    if (threadIdx.x == 0) finalize_state(A, B, status, fp);
 }
 
 __global__ void k_status_reset(dev_status *status, int hist_base) {
@@ -485,7 +308,7 @@ __global__ void k_status_reset(dev_status *status, int hist_base) {
 __global__ void __launch_bounds__(FIN_BLOCK)
     k_reduce_only(const double *__restrict__ partials, int nparts, double *out2) {
     double A, B;
-    fixed_order_sum(partials, nparts, A, B);
+    fixed_order_sum<FIN_BLOCK>(partials, nparts, A, B);
     if (threadIdx.x == 0) {
         out2[0] = A;
         out2[1] = B;
@@ -861,94 +684,38 @@ hipError_t launch_unpack_links(const void *L64, double *Uaos, long V, hipStream_
 
 template <class T>
 hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *partials,
-                             const dev_status *status, hipStream_t st) {
+                             dev_status *status, const fin_params &fp, hipStream_t st) {
     k_div_reduce<T><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
-        g, static_cast<const vec2_t<T> *>(L), static_cast<vec2_t<T> *>(D), partials, status);
+        g, static_cast<const vec2_t<T> *>(L), static_cast<vec2_t<T> *>(D), partials, status, fp);
     return hipGetLastError();
 }
 template hipError_t launch_div_reduce<double>(const geom &, const void *, void *, double *,
-                                              const dev_status *, hipStream_t);
+                                              dev_status *, const fin_params &, hipStream_t);
 template hipError_t launch_div_reduce<float>(const geom &, const void *, void *, double *,
-                                             const dev_status *, hipStream_t);
+                                             dev_status *, const fin_params &, hipStream_t);
 
 template <class T>
 hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void *LD, void *Dout,
-                         void *G, T c, double *partials, const dev_status *status, hipStream_t st) {
+                         void *G, T c, double *partials, dev_status *status, const fin_params &fp,
+                         hipStream_t st) {
     if (G)
         k_update<T, true><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
             g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout),
             static_cast<const vec2_t<T> *>(LD), static_cast<vec2_t<T> *>(Dout),
-            static_cast<vec2_t<T> *>(G), c, partials, status);
+            static_cast<vec2_t<T> *>(G), c, partials, status, fp);
     else
         k_update<T, false><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
             g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout),
             static_cast<const vec2_t<T> *>(LD), static_cast<vec2_t<T> *>(Dout), nullptr, c,
-            partials, status);
+            partials, status, fp);
     return hipGetLastError();
 }
 template hipError_t launch_update<double>(const geom &, const void *, void *, const void *, void *,
-                                          void *, double, double *, const dev_status *, hipStream_t);
+                                          void *, double, double *, dev_status *,
+                                          const fin_params &, hipStream_t);
 template hipError_t launch_update<float>(const geom &, const void *, void *, const void *, void *,
-                                         void *, float, double *, const dev_status *, hipStream_t);
-
-template <class T>
-hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const dev_status *status,
-                         hipStream_t st) {
-    dim3 grid((unsigned)(g.Lz * g.Lt), 4);
-    const size_t lds = (size_t)g.Ly * (g.Lx + 1) * sizeof(vec2_t<T>);
-    if (dir < 0)
-        k_fft_xy<T, -1><<<grid, XY_BLOCK, lds, st>>>(g, static_cast<vec2_t<T> *>(D),
-                                                     static_cast<const vec2_t<T> *>(tw), status);
-    else
-        k_fft_xy<T, +1><<<grid, XY_BLOCK, lds, st>>>(g, static_cast<vec2_t<T> *>(D),
-                                                     static_cast<const vec2_t<T> *>(tw), status);
-    return hipGetLastError();
-}
-template hipError_t launch_fft_xy<double>(const geom &, void *, int, const void *,
-                                          const dev_status *, hipStream_t);
-template hipError_t launch_fft_xy<float>(const geom &, void *, int, const void *,
-                                         const dev_status *, hipStream_t);
-
-template <class T> size_t fft_zt_lds_bytes(const geom &g, int W) {
-    return (size_t)g.Lt * ((size_t)g.Lz * W + ZT_PAD) * sizeof(vec2_t<T>);
-}
-template size_t fft_zt_lds_bytes<double>(const geom &, int);
-template size_t fft_zt_lds_bytes<float>(const geom &, int);
-
-template <class T> hipError_t fft_zt_set_max_lds(size_t bytes) {
-    hipError_t e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_zt<T, 0>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_zt<T, -1>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_zt<T, 1>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-template hipError_t fft_zt_set_max_lds<double>(size_t);
-template hipError_t fft_zt_set_max_lds<float>(size_t);
-
-template <class T>
-hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const T *ptab,
-                         T p2max_over_V, int W, const dev_status *status, hipStream_t st) {
-    const long Lxy = (long)g.Lx * g.Ly;
-    dim3 grid((unsigned)((Lxy + W - 1) / W), 4);
-    const size_t lds = fft_zt_lds_bytes<T>(g, W);
-    auto Dp = static_cast<vec2_t<T> *>(D);
-    auto twp = static_cast<const vec2_t<T> *>(tw);
-    if (mode == 0)
-        k_fft_zt<T, 0><<<grid, ZT_BLOCK, lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W, status);
-    else if (mode < 0)
-        k_fft_zt<T, -1><<<grid, ZT_BLOCK, lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W, status);
-    else
-        k_fft_zt<T, 1><<<grid, ZT_BLOCK, lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W, status);
-    return hipGetLastError();
-}
-template hipError_t launch_fft_zt<double>(const geom &, void *, int, const void *, const double *,
-                                          double, int, const dev_status *, hipStream_t);
-template hipError_t launch_fft_zt<float>(const geom &, void *, int, const void *, const float *,
-                                         float, int, const dev_status *, hipStream_t);
+                                         void *, float, double *, dev_status *, const fin_params &,
+                                         hipStream_t);
 
 hipError_t launch_reorder_fields(const geom &g, const double2 *in, double2 *out, int to_natural,
                                  hipStream_t st) {
@@ -956,11 +723,9 @@ hipError_t launch_reorder_fields(const geom &g, const double2 *in, double2 *out,
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double *partials, int nparts, dev_status *status, double normF,
-                           double normT, double tol, int max_iter, int increment, double *histF,
-                           double *histT, int hist_cap, hipStream_t st) {
-    k_finalize<<<1, FIN_BLOCK, 0, st>>>(partials, nparts, status, normF, normT, tol, max_iter,
-                                        increment, histF, histT, hist_cap);
+hipError_t launch_finalize(const double *partials, int nparts, dev_status *status,
+                           const fin_params &fp, hipStream_t st) {
+    k_finalize<<<1, FIN_BLOCK, 0, st>>>(partials, nparts, status, fp);
     return hipGetLastError();
 }
 

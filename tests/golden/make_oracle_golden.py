@@ -24,6 +24,7 @@ import oracle  # noqa: E402
 WORKLOADS = {
     "32^4": {"L": (32, 32, 32, 32), "eps": [0.6, 0.45, 0.35], "alpha": 0.08, "tol": 1e-15},
     "8^4": {"L": (8, 8, 8, 8), "eps": [0.5], "alpha": 0.08, "tol": 1e-12},
+    "48^3x96": {"L": (48, 48, 48, 96), "eps": [0.45], "alpha": 0.08, "tol": 1e-15},
 }
 
 

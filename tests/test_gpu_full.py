@@ -1,0 +1,80 @@
+"""Full-size parity at the paper's 32^4 shape (GPU).
+
+The reference values in tests/golden/oracle_324.json were written by
+tests/golden/make_oracle_golden.py, which calls only the CPU oracle and the
+input generator (about 100 s per solve on 8 cores).  Here the GPU solves the
+same seeded inputs, FP64 and mixed precision, and the oracle re-measures the
+returned links: theta < 1e-15, |F - F_oracle| <= 1e-12, plaquette drift
+<= 1e-12, unitarity <= 1e-13.  One sweep is also compared link by link.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+L = (32, 32, 32, 32)
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_324.json")
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        return {r["eps"]: r for r in json.load(f)["runs"]}
+
+
+def gpu(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def configs():
+    return {}
+
+
+def _config(configs, eps):
+    if eps not in configs:
+        configs.clear()  # keep host memory bounded: one 32^4 field at a time
+        configs[eps] = inputs.make_config(L, eps, inputs.CONFIG_SEEDS[("32^4", eps)])[0]
+    return configs[eps]
+
+
+@pytest.mark.parametrize("eps", [0.6, 0.45, 0.35])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_32x4(lgf_gpu, configs, eps, precision):
+    ref = _golden()[eps]
+    U = _config(configs, eps)
+    assert oracle.plaquette(U) == pytest.approx(ref["plaquette_in"], abs=1e-13)
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, 0.08, 1e-15, precision=precision, max_iter=2000)
+    assert r.status == 0
+    out = Ug.cpu().numpy()
+    del Ug
+    assert oracle.theta(out) < 1e-15
+    assert abs(r.F - ref["F"]) <= 1e-12
+    assert abs(oracle.F(out) - ref["F"]) <= 1e-12
+    assert abs(oracle.plaquette(out) - ref["plaquette_in"]) <= 1e-12
+    mu, md = oracle.unitarity(out)
+    assert mu <= 1e-13 and md <= 1e-13
+    if precision == "fp64":
+        assert abs(r.iterations - ref["iterations"]) <= 1
+    else:
+        assert 0 < r.fp32_iterations < r.iterations
+
+
+def test_lockstep_sweep_32x4(lgf_gpu, configs):
+    U = _config(configs, 0.45)
+    Ug = gpu(U)
+    r = lgf_gpu.iterate(Ug, 0.08, 1)
+    got = Ug.cpu().numpy()
+    del Ug
+    ref = oracle.iterate(U, 0.08, 1)
+    assert np.max(np.abs(got - ref)) < 1e-13
+    assert r.theta == pytest.approx(_golden()[0.45]["theta_hist"][1], rel=1e-11)
+    assert r.F == pytest.approx(_golden()[0.45]["F_hist"][1], abs=1e-14)

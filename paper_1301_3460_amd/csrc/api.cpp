@@ -62,7 +62,6 @@ struct lgf_ctx {
     double *reduce_host = nullptr;      // pinned [2]
     double *histF = nullptr, *histT = nullptr;
     int hist_len = 0;
-    unsigned *counter = nullptr;  // last-block counter of the sweep kernels
     // differentiation scratch (allocated on first use)
     double *gaos = nullptr;   // V*9 complex or 4V*9 complex (link exponentials)
     double2 *Lrot = nullptr;  // SoA-12 FP64 links
@@ -102,7 +101,6 @@ fin_params finp(const lgf_ctx *c, bool enabled, double tol = 0, int max_iter = 0
     f.enabled = enabled ? 1 : 0;
     f.histF = c->histF;
     f.histT = c->histT;
-    f.counter = c->counter;
     return f;
 }
 
@@ -307,8 +305,10 @@ int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
         chk(hipEventRecord(e[3], c->stream));
         chk(launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
                              accG ? c->G32 : nullptr, half_alpha, c->partials, c->status,
-                             finp(c, true, 0.0, n + 1, 1), c->stream));
+                             finp(c, false), c->stream));
         chk(hipEventRecord(e[4], c->stream));
+        chk(launch_finalize(c->partials, c->nparts, c->status, finp(c, true, 0.0, n + 1, 1),
+                            c->stream));
         chk(hipEventRecord(e[5], c->stream));
         if (err != hipSuccess) rc = fail(c, LGF_ERR_DEVICE, hipGetErrorString(err));
     }
@@ -379,7 +379,6 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
     ok = ok && alloc((void **)&c->reduce_out, 2 * sizeof(double));
     ok = ok && alloc((void **)&c->histF, HIST_CAP * sizeof(double));
     ok = ok && alloc((void **)&c->histT, HIST_CAP * sizeof(double));
-    ok = ok && alloc((void **)&c->counter, sizeof(unsigned));
     ok = ok && hipHostMalloc((void **)&c->status_host, sizeof(dev_status), 0) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->reduce_host, 2 * sizeof(double), 0) == hipSuccess;
     if (!ok) {
@@ -398,7 +397,6 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
     std::vector<double> pt64(pt.begin(), pt.end());
     std::vector<float> pt32(pt.begin(), pt.end());
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = hipMemset(c->counter, 0, sizeof(unsigned));
     if (e == hipSuccess) e = hipMemcpy(c->tw64, tw64.data(), TW_M * sizeof(double2), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->tw32, tw32.data(), TW_M * sizeof(float2), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->pt64, pt64.data(), nt * sizeof(double), hipMemcpyHostToDevice);
@@ -424,7 +422,7 @@ void lgf_destroy(lgf_ctx *c) {
     else (void)hipDeviceSynchronize();
     void *dev[] = {c->L64[0], c->L64[1], c->D64[0], c->D64[1], c->G32, c->tw64, c->tw32,
                    c->pt64, c->pt32, c->partials, c->status, c->reduce_out, c->histF, c->histT,
-                   c->gaos, c->Lrot, c->counter};
+                   c->gaos, c->Lrot};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->status_host) (void)hipHostFree(c->status_host);

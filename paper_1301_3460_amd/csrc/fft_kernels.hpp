@@ -11,6 +11,26 @@ namespace lgf {
 
 static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// 1/x from the hardware estimate refined by Newton steps (to about 1 ulp).
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+__device__ __forceinline__ float recip(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// Momentum-space factor p2max/(V p2) of one (z,t) column: `base` is the
+// column's p2 without the z term (negative for a padding column).
+template <class T>
+__device__ __forceinline__ T fa_factor(T base, T pz, T p2max_over_V) {
+    const T p2 = base + pz;
+    return (base < T(0) || p2 == T(0)) ? T(0) : p2max_over_V * recip(p2);
+}
+
 // ---------------------------------------------------------------------------
 // (x, y) plane transform: one plane of one field per block, LDS [y][x+1]
 // ---------------------------------------------------------------------------
@@ -109,14 +129,13 @@ __global__ void __launch_bounds__(ZT_BLOCK)
     if (MODE == 0) {
         const T *px = ptab, *py = ptab + g.Lx, *pz = ptab + g.Lx + g.Ly,
                 *pt = ptab + g.Lx + g.Ly + g.Lz;
-        const int Lx = g.Lx;
+        const int Lx = g.Lx, s0i = (int)s0, Lxyi = (int)Lxy;
+        // column c = w + W*z along t: element j is at t position j
         auto scale = [=](int c, int j) -> T {
-            const int w = c % W, z = c / W;
-            const long sxy = s0 + w;
-            if (sxy >= Lxy) return T(0);  // padding column of a ragged tile
-            const int x = (int)(sxy % Lx), y = (int)(sxy / Lx);
-            const T p2 = (px[x] + py[y]) + (pz[z] + pt[j]);
-            return p2 == T(0) ? T(0) : p2max_over_V / p2;
+            const int sxy = s0i + (c % W);
+            if (sxy >= Lxyi) return T(0);  // padding column of a ragged tile
+            const int y = sxy / Lx, x = sxy - y * Lx;
+            return fa_factor<T>((px[x] + py[y]) + pz[c / W], pt[j], p2max_over_V);
         };
         switch (Lt) {
 #define LGF_TCASE(NN) \
@@ -197,32 +216,34 @@ __device__ __forceinline__ void exchange_axis(cpx<T> (&a)[NA], int w, int b, int
     }
 }
 
-// Column transform forward, times scale(c, position), inverse: one register
-// pass when the extent is at most 32, else three LDS passes.
-template <int N, class T, class Base, class Scale>
+// Column transform forward, times scale(info, position), inverse, in one
+// register pass (extent up to 32); info = prep(c) is computed once per column.
+template <int N, class T, class Base, class Prep, class Scale>
 __device__ __forceinline__ void col_fwd_scale_inv_n(vec2_t<T> *lds, int ncols, int stride, Base base,
-                                                    Scale scale, const vec2_t<T> *__restrict__ tw) {
+                                                    Prep prep, Scale scale,
+                                                    const vec2_t<T> *__restrict__ tw) {
     for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
         const int b0 = base(c);
+        const auto info = prep(c);
         cpx<T> v[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] = ld<T>(lds + b0 + k * stride);
         dft<N, -1>(v, tw);
 #pragma unroll
-        for (int k = 0; k < N; ++k) v[k] = scale(c, k) * v[k];
+        for (int k = 0; k < N; ++k) v[k] = scale(info, k) * v[k];
         dft<N, +1>(v, tw);
 #pragma unroll
         for (int k = 0; k < N; ++k) st<T>(lds + b0 + k * stride, v[k]);
     }
 }
 
-template <class T, class Base, class Scale>
+template <class T, class Base, class Prep, class Scale>
 __device__ __forceinline__ void col_fwd_scale_inv(int n, vec2_t<T> *lds, int ncols, int stride,
-                                                  Base base, Scale scale,
+                                                  Base base, Prep prep, Scale scale,
                                                   const vec2_t<T> *__restrict__ tw) {
     switch (n) {
 #define LGF_SCASE(NN) \
-    case NN: col_fwd_scale_inv_n<NN, T>(lds, ncols, stride, base, scale, tw); break;
+    case NN: col_fwd_scale_inv_n<NN, T>(lds, ncols, stride, base, prep, scale, tw); break;
         LGF_SCASE(2) LGF_SCASE(3) LGF_SCASE(4) LGF_SCASE(6) LGF_SCASE(8) LGF_SCASE(12)
         LGF_SCASE(16) LGF_SCASE(24) LGF_SCASE(32)
 #undef LGF_SCASE
@@ -302,16 +323,17 @@ __global__ void __launch_bounds__(rc_max_threads<T>())
     if (MODE == 0) {
         const T *px = ptab, *py = ptab + g.Lx, *pz = ptab + g.Lx + g.Ly,
                 *pt = ptab + g.Lx + g.Ly + g.Lz;
-        const int Lx = g.Lx;
+        const int Lx = g.Lx, s0i = (int)s0, Lxyi = (int)Lxy;
         auto col = [&](int c0, int C) {
-            auto scale = [=](int c, int k) -> T {
-                const long sxy = s0 + (c % W);
-                if (sxy >= Lxy) return T(0);  // padding column of a ragged tile
-                const int x = (int)(sxy % Lx), y = (int)(sxy / Lx);
-                const T p2 = (px[x] + py[y]) + (pz[k] + pt[c0 + c / W]);
-                return p2 == T(0) ? T(0) : p2max_over_V / p2;
+            // column c = w + W*j along z at t position c0 + j
+            auto prep = [=](int c) -> T {
+                const int sxy = s0i + (c % W);
+                if (sxy >= Lxyi) return T(-1);  // padding column of a ragged tile
+                const int y = sxy / Lx, x = sxy - y * Lx;
+                return (px[x] + py[y]) + pt[c0 + c / W];
             };
-            col_fwd_scale_inv<T>(Lz, lds, W * C, W, base, scale, tw);
+            auto scale = [=](T base, int k) -> T { return fa_factor<T>(base, pz[k], p2max_over_V); };
+            col_fwd_scale_inv<T>(Lz, lds, W * C, W, base, prep, scale, tw);
         };
         exchange_axis<NT, T>(a, w, z, W, 1, PJ, lds, col);
     } else {

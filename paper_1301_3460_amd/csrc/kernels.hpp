@@ -20,14 +20,13 @@ struct dev_status {
 enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXITER = 4, ST_NONFINITE = 5, ST_DIVERGING = 6 };
 constexpr int DIVERGE_RISES = 8;
 
-// Stopping test run by the last block of a sweep kernel to finish (it sums
-// the per-block partials in fixed order, so the result does not depend on
-// which block that is).  enabled == 0: partials only.
+// Stopping test after a sweep kernel: a one-block kernel sums the per-block
+// partials in fixed order and updates the device status (enabled == 0: the
+// sweep kernel only writes its partials).
 struct fin_params {
     double normF, normT, tol;
     int max_iter, increment, hist_cap, enabled;
     double *histF, *histT;
-    unsigned *counter;  // zero between launches; reset by the last block
 };
 
 struct geom {

@@ -82,7 +82,7 @@ __global__ void k_matrix_from_field(const double2 *__restrict__ D, double2 *__re
 // finalize: fixed-order sum of block partials and the stopping test
 // ---------------------------------------------------------------------------
 
-constexpr int FIN_BLOCK = 256;
+constexpr int FIN_BLOCK = 1024;
 
 template <int NT>
 __device__ __forceinline__ void fixed_order_sum(const volatile double *partials, int nparts,
@@ -140,30 +140,6 @@ __device__ __forceinline__ void finalize_state(double A, double B, dev_status *s
     *status = st;
 }
 
-// Called by every block after its partial is written: the last block to
-// arrive sums all partials (fixed order) and runs the stopping test.
-template <int NT>
-__device__ __forceinline__ void last_block_finalize(double *partials, int nparts,
-                                                    dev_status *status, const fin_params &fp) {
-    if (!fp.enabled) return;
-    __shared__ int am_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(fp.counter, 1u);
-        am_last = (prev == (unsigned)nparts - 1);
-    }
-    __syncthreads();
-    if (!am_last) return;
-    __threadfence();
-    double A, B;
-    fixed_order_sum<NT>(partials, nparts, A, B);
-    if (threadIdx.x == 0) {
-        finalize_state(A, B, status, fp);
-        atomicExch(fp.counter, 0u);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // divergence and reductions of given links (first sweep of a solve)
 // ---------------------------------------------------------------------------
@@ -171,7 +147,7 @@ __device__ __forceinline__ void last_block_finalize(double *partials, int nparts
 template <class T>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_div_reduce(geom g, const vec2_t<T> *__restrict__ L, vec2_t<T> *__restrict__ D,
-                 double *__restrict__ partials, dev_status *__restrict__ status, fin_params fp) {
+                 double *__restrict__ partials, const dev_status *__restrict__ status) {
     if (status->done) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const long s = (long)b * SITE_BLOCK + threadIdx.x;
@@ -198,7 +174,6 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         st<T>(D + 3 * g.V + s, f3);
     }
     block_sum2<SITE_BLOCK>(fs, ts, partials, b);
-    last_block_finalize<SITE_BLOCK>(partials, gridDim.x, status, fp);
 }
 
 // ---------------------------------------------------------------------------
@@ -210,7 +185,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
     k_update(geom g, const vec2_t<T> *__restrict__ Lin, vec2_t<T> *__restrict__ Lout,
              const vec2_t<T> *__restrict__ LD, vec2_t<T> *__restrict__ Dout,
              vec2_t<T> *__restrict__ G, T c, double *__restrict__ partials,
-             dev_status *__restrict__ status, fin_params fp) {
+             const dev_status *__restrict__ status) {
     if (status->done) return;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const long s = (long)b * SITE_BLOCK + threadIdx.x;
@@ -259,7 +234,6 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         }
     }
     block_sum2<SITE_BLOCK>(fs, ts, partials, b);
-    last_block_finalize<SITE_BLOCK>(partials, gridDim.x, status, fp);
 }
 
 // reorder 4 fields between natural index order and transform-position order
@@ -686,7 +660,8 @@ template <class T>
 hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *partials,
                              dev_status *status, const fin_params &fp, hipStream_t st) {
     k_div_reduce<T><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
-        g, static_cast<const vec2_t<T> *>(L), static_cast<vec2_t<T> *>(D), partials, status, fp);
+        g, static_cast<const vec2_t<T> *>(L), static_cast<vec2_t<T> *>(D), partials, status);
+    if (fp.enabled) k_finalize<<<1, FIN_BLOCK, 0, st>>>(partials, site_blocks(g.V), status, fp);
     return hipGetLastError();
 }
 template hipError_t launch_div_reduce<double>(const geom &, const void *, void *, double *,
@@ -702,12 +677,13 @@ hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void 
         k_update<T, true><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
             g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout),
             static_cast<const vec2_t<T> *>(LD), static_cast<vec2_t<T> *>(Dout),
-            static_cast<vec2_t<T> *>(G), c, partials, status, fp);
+            static_cast<vec2_t<T> *>(G), c, partials, status);
     else
         k_update<T, false><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
             g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout),
             static_cast<const vec2_t<T> *>(LD), static_cast<vec2_t<T> *>(Dout), nullptr, c,
-            partials, status, fp);
+            partials, status);
+    if (fp.enabled) k_finalize<<<1, FIN_BLOCK, 0, st>>>(partials, site_blocks(g.V), status, fp);
     return hipGetLastError();
 }
 template hipError_t launch_update<double>(const geom &, const void *, void *, const void *, void *,

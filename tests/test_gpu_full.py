@@ -78,3 +78,34 @@ def test_lockstep_sweep_32x4(lgf_gpu, configs):
     assert np.max(np.abs(got - ref)) < 1e-13
     assert r.theta == pytest.approx(_golden()[0.45]["theta_hist"][1], rel=1e-11)
     assert r.F == pytest.approx(_golden()[0.45]["F_hist"][1], abs=1e-14)
+
+
+GOLDEN48 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "oracle_483x96.json")
+L48 = (48, 48, 48, 96)
+
+
+@pytest.fixture(scope="module")
+def config48():
+    return inputs.make_config(L48, 0.45, inputs.CONFIG_SEEDS[("48^3x96", 0.45)])[0]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_48x3x96(lgf_gpu, config48, precision):
+    """10.6M sites: radix-3 and two-pass transform extents at scale."""
+    with open(GOLDEN48) as f:
+        ref = json.load(f)["runs"][0]
+    U = config48
+    assert oracle.plaquette(U) == pytest.approx(ref["plaquette_in"], abs=1e-13)
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, 0.08, 1e-15, precision=precision, max_iter=2000)
+    assert r.status == 0
+    out = Ug.cpu().numpy()
+    del Ug
+    assert oracle.theta(out) < 1e-15
+    assert abs(r.F - ref["F"]) <= 1e-12
+    assert abs(oracle.plaquette(out) - ref["plaquette_in"]) <= 1e-12
+    mu, md = oracle.unitarity(out)
+    assert mu <= 1e-13 and md <= 1e-13
+    if precision == "fp64":
+        assert abs(r.iterations - ref["iterations"]) <= 1

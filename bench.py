@@ -33,8 +33,36 @@ BYTES_PER_SITE = {
 }
 
 
+# sources that determine the update kernel's code (for the traffic record)
+UPDATE_SOURCES = ("paper_1301_3460_amd/csrc/sweep.hip", "paper_1301_3460_amd/csrc/common.hpp",
+                  "paper_1301_3460_amd/csrc/su3.hpp", "paper_1301_3460_amd/csrc/kernels.hpp")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "update_32x4_fp64_traffic.json")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def sources_sha256(paths=UPDATE_SOURCES) -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per update launch from the committed rocprofv3 counter record,
+    or None when the kernel sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_RECORD):
+        return None
+    with open(TRAFFIC_RECORD) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != sources_sha256():
+        return None
+    return rec["read_bytes"] + rec["write_bytes"]
 
 
 def main() -> int:
@@ -44,7 +72,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--solves", type=int, default=5, help="repeats per time-to-theta solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sweeps", type=int, default=4)
+    ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--sweeps-only", action="store_true",
                     help="only the timed sweeps, the per-kernel timing and one device copy of "
                          "the 32^4 link field (a known-size reference for HBM counters)")
@@ -178,7 +206,8 @@ def main() -> int:
                                f"alpha={ALPHA}, eps={EPS_MAIN} links + Haar gauge transformation",
                    "lattice": list(L), "sites": V},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(),
                      "kernel": "k_update<double> (update + next divergence)",
                      "bytes_per_site": BYTES_PER_SITE["fp64"]["update"]},
         "cpu_baseline": cpu,

@@ -92,6 +92,12 @@ void lgf_destroy(lgf_ctx *ctx);
 /* Threshold at which LGF_MIXED hands over from FP32 to FP64 (default 1e-8). */
 int lgf_set_theta_switch(lgf_ctx *ctx, double theta_switch);
 
+/* on != 0 (default): Fourier-accelerated steepest descent.  on == 0: plain
+ * steepest descent, g = reunit(1 + (alpha/2) Delta) with no transform -- the
+ * method the paper accelerates, which slows down on large lattices (the
+ * paragraph after the display equation). */
+int lgf_set_acceleration(lgf_ctx *ctx, int on);
+
 /* Exactly n_iter Fourier-accelerated updates of the links U (in place), with
  * no stopping test (n_iter >= 0).  res (may be NULL) gets F and theta of the
  * returned links.  LGF_FP64 only semantics: a LGF_MIXED context runs the

@@ -63,6 +63,9 @@ def _load():
         "orc_fix": (_c.c_int, [_ip, _zp, _c.c_double, _c.c_double, _c.c_int,
                                _c.POINTER(_c.c_int), _c.POINTER(_c.c_double),
                                _c.POINTER(_c.c_double), _dp, _dp]),
+        "orc_fix_ex": (_c.c_int, [_ip, _zp, _c.c_double, _c.c_double, _c.c_int, _c.c_int,
+                                  _c.POINTER(_c.c_int), _c.POINTER(_c.c_double),
+                                  _c.POINTER(_c.c_double), _dp, _dp]),
         "orc_plaquette": (_c.c_double, [_ip, _zp]),
         "orc_unitarity": (None, [_zp, _c.c_int64, _c.POINTER(_c.c_double),
                                  _c.POINTER(_c.c_double)]),
@@ -185,18 +188,21 @@ def iterate(U, alpha: float, n: int) -> np.ndarray:
     return U
 
 
-def fix(U, alpha: float = 0.08, tol: float = 1e-15, max_iter: int = 10000):
+def fix(U, alpha: float = 0.08, tol: float = 1e-15, max_iter: int = 10000,
+        accelerate: bool = True):
     """Gauge fixing to theta < tol.  Returns a dict with the links, the number
     of updates, F and theta of the returned links, their per-iteration
-    histories and a status (0 converged, 1 max_iter, 2 non-finite)."""
+    histories and a status (0 converged, 1 max_iter, 2 non-finite).
+    accelerate=False: plain steepest descent (no Fourier acceleration)."""
     U = _z(U).copy()
     it = ctypes.c_int(0)
     f = ctypes.c_double(0)
     th = ctypes.c_double(0)
     Fh = np.zeros(max_iter + 1)
     Th = np.zeros(max_iter + 1)
-    st = _load().orc_fix(_L_of_links(U), U, float(alpha), float(tol), int(max_iter),
-                         ctypes.byref(it), ctypes.byref(f), ctypes.byref(th), Fh, Th)
+    st = _load().orc_fix_ex(_L_of_links(U), U, float(alpha), float(tol), int(max_iter),
+                            1 if accelerate else 0, ctypes.byref(it), ctypes.byref(f),
+                            ctypes.byref(th), Fh, Th)
     n = it.value
     return {"U": U, "iterations": n, "F": f.value, "theta": th.value,
             "F_hist": Fh[:n + 1], "theta_hist": Th[:n + 1], "status": int(st)}

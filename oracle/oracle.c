@@ -443,8 +443,20 @@ int orc_iterate(const int *L, cplx *U, double alpha, int n) {
  * F_hist/theta_hist (may be NULL) receive F_n, theta_n for n = 0..*iters.
  * Returns 0 if converged, 1 if max_iter was reached, 2 on non-finite theta.
  */
+int orc_fix_ex(const int *L, cplx *U, double alpha, double tol, int max_iter, int accelerate,
+               int *iters, double *F, double *theta, double *F_hist, double *theta_hist);
+
 int orc_fix(const int *L, cplx *U, double alpha, double tol, int max_iter,
             int *iters, double *F, double *theta, double *F_hist, double *theta_hist) {
+    return orc_fix_ex(L, U, alpha, tol, max_iter, 1, iters, F, theta, F_hist, theta_hist);
+}
+
+/*
+ * As orc_fix; accelerate == 0 gives plain steepest descent (the method before
+ * Fourier acceleration): g = reunit(1 + (alpha/2) Delta), no transform.
+ */
+int orc_fix_ex(const int *L, cplx *U, double alpha, double tol, int max_iter, int accelerate,
+               int *iters, double *F, double *theta, double *F_hist, double *theta_hist) {
     const int64_t V = volume(L);
     cplx *D = malloc(sizeof(cplx) * 9 * V);
     cplx *LD = malloc(sizeof(cplx) * 9 * V);
@@ -460,7 +472,11 @@ int orc_fix(const int *L, cplx *U, double alpha, double tol, int max_iter,
         if (!isfinite(th)) { status = 2; break; }
         if (th < tol) { status = 0; break; }
         if (n >= max_iter) { status = 1; break; }
-        if (orc_fourier_accelerate(L, D, LD)) { status = 2; break; }
+        if (accelerate) {
+            if (orc_fourier_accelerate(L, D, LD)) { status = 2; break; }
+        } else {
+            memcpy(LD, D, sizeof(cplx) * 9 * V);
+        }
 #pragma omp parallel for schedule(static)
         for (int64_t s = 0; s < V; ++s) {
             cplx M[9];

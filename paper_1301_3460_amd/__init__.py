@@ -85,6 +85,7 @@ def load(path: str | None = None):
         "lgf_create": (c.c_int, [c.POINTER(vp), c.POINTER(c.c_int * 4), c.c_int, vp]),
         "lgf_destroy": (None, [vp]),
         "lgf_set_theta_switch": (c.c_int, [vp, c.c_double]),
+        "lgf_set_acceleration": (c.c_int, [vp, c.c_int]),
         "lgf_iterate": (c.c_int, [vp, vp, c.c_double, c.c_int, c.POINTER(_Result)]),
         "lgf_fix": (c.c_int, [vp, vp, c.c_double, c.c_double, c.c_int, c.POINTER(_Result)]),
         "lgf_functional": (c.c_int, [vp, vp, vp, dp]),
@@ -173,6 +174,12 @@ class Context:
         import torch
 
         return _check(U, torch.complex128, (4,) + self._site_shape() + (3, 3), name)
+
+    def set_acceleration(self, on: bool):
+        """True: Fourier-accelerated steepest descent; False: plain steepest descent."""
+        rc = self._lib.lgf_set_acceleration(self._h, 1 if on else 0)
+        if rc:
+            self._err(rc)
 
     def set_theta_switch(self, th: float):
         rc = self._lib.lgf_set_theta_switch(self._h, float(th))
@@ -330,16 +337,21 @@ def _ctx(U, precision="fp64") -> Context:
     return _ctx_for(_lattice_of_links(U), U.device, precision)
 
 
-def fix(U, alpha=0.08, theta_tol=1e-15, precision="fp64", max_iter=10000, theta_switch=1e-8):
-    """Gauge-fix U in place; returns a Result (iterations, F, theta, status)."""
+def fix(U, alpha=0.08, theta_tol=1e-15, precision="fp64", max_iter=10000, theta_switch=1e-8,
+        accelerate=True):
+    """Gauge-fix U in place; returns a Result (iterations, F, theta, status).
+    accelerate=False runs plain (unaccelerated) steepest descent."""
     c = _ctx(U, precision)
     if precision == "mixed":
         c.set_theta_switch(theta_switch)
+    c.set_acceleration(accelerate)
     return c.fix(U, alpha, theta_tol, max_iter)
 
 
-def iterate(U, alpha=0.08, n=1, precision="fp64"):
-    return _ctx(U, precision).iterate(U, alpha, n)
+def iterate(U, alpha=0.08, n=1, precision="fp64", accelerate=True):
+    c = _ctx(U, precision)
+    c.set_acceleration(accelerate)
+    return c.iterate(U, alpha, n)
 
 
 def functional(U, g=None):

@@ -40,6 +40,7 @@ struct lgf_ctx {
     hipStream_t stream = nullptr;
     double p2max = 0;
     double theta_switch = 1e-8;
+    bool accelerate = true;  // false: plain steepest descent (no transform)
 
     // working links, SoA-12: FP64 double buffer; the FP32 pair aliases L64[1]
     double2 *L64[2] = {nullptr, nullptr};
@@ -165,11 +166,15 @@ hipError_t enqueue_sweep(lgf_ctx *c, int cur, T half_alpha, bool accG, const fin
     using P = prec<T>;
     hipError_t e;
     void *D = P::field(c, cur);
-    if ((e = launch_fft_xy<T>(c->g, D, -1, P::tw(c), c->status, c->stream)) != hipSuccess) return e;
-    if ((e = launch_fft_zt<T>(c->g, D, 0, P::tw(c), P::pt(c), (T)(c->p2max / (double)c->g.V),
-                              P::W(c), c->status, c->stream)) != hipSuccess)
-        return e;
-    if ((e = launch_fft_xy<T>(c->g, D, +1, P::tw(c), c->status, c->stream)) != hipSuccess) return e;
+    if (c->accelerate) {
+        if ((e = launch_fft_xy<T>(c->g, D, -1, P::tw(c), c->status, c->stream)) != hipSuccess)
+            return e;
+        if ((e = launch_fft_zt<T>(c->g, D, 0, P::tw(c), P::pt(c), (T)(c->p2max / (double)c->g.V),
+                                  P::W(c), c->status, c->stream)) != hipSuccess)
+            return e;
+        if ((e = launch_fft_xy<T>(c->g, D, +1, P::tw(c), c->status, c->stream)) != hipSuccess)
+            return e;
+    }
     return launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
                             accG ? c->G32 : nullptr, half_alpha, c->partials, c->status, fp,
                             c->stream);
@@ -354,6 +359,7 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
     c->g.Lz = L[2];
     c->g.Lt = L[3];
     c->g.V = (long)L[0] * L[1] * L[2] * L[3];
+    c->g.zper = ((long)L[0] * L[1] % SITE_BLOCK == 0 && L[2] % 8 == 0) ? L[2] / 8 : 0;
     c->precision = precision;
     c->stream = static_cast<hipStream_t>(stream);
     if (hipGetDevice(&c->device) != hipSuccess) {
@@ -428,6 +434,12 @@ void lgf_destroy(lgf_ctx *c) {
     if (c->status_host) (void)hipHostFree(c->status_host);
     if (c->reduce_host) (void)hipHostFree(c->reduce_host);
     delete c;
+}
+
+int lgf_set_acceleration(lgf_ctx *c, int on) {
+    if (!c) return LGF_ERR_ARG;
+    c->accelerate = on != 0;
+    return LGF_OK;
 }
 
 int lgf_set_theta_switch(lgf_ctx *c, double theta_switch) {

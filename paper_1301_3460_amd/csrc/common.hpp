@@ -17,6 +17,19 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + (x < r ? x : r) + k;
 }
 
+// First site of site-kernel block b.  With g.zper > 0 every XCD (blocks
+// b % 8) owns a slab of zper consecutive z planes and walks it z fastest, then
+// t, then the SITE_BLOCK-site segment of the xy-plane: the z and t neighbours
+// a block reads were loaded a few blocks earlier on the same XCD (same L2).
+__device__ __forceinline__ long block_first_site(const geom &g, int b, int nb) {
+    if (g.zper <= 0) return (long)xcd_block(b, nb) * SITE_BLOCK;
+    const int x = b & 7, k = b >> 3;
+    const int zz = k % g.zper, rest = k / g.zper;
+    const int t = rest % g.Lt, q = rest / g.Lt;
+    const int z = x * g.zper + zz;
+    return (long)q * SITE_BLOCK + (long)g.Lx * g.Ly * (z + (long)g.Lz * t);
+}
+
 struct nbr {
     long p[4], m[4];  // s + mu, s - mu (periodic)
 };

@@ -180,40 +180,26 @@ __global__ void __launch_bounds__(ZT_BLOCK)
 // Each thread keeps the whole column of one strided lattice axis (t for the
 // (z,t) pass, y for the (x,y) pass) in registers, loaded straight from HBM so
 // that consecutive lanes read consecutive sites.  The other axis is
-// transformed through LDS in chunks of a few register positions: every thread
-// writes its chunk, the columns of the exchanged axis are transformed, and the
-// values are read back.  LDS element (w, b, j) of a chunk is at
-// j*PJ + b*SB + w*SW.
+// transformed through LDS: every thread writes its whole column, the columns
+// of the exchanged axis are transformed by all threads at once, and the values
+// are read back (the register copy is dead meanwhile, which keeps the register
+// peak down).  LDS element (w, b, j) is at j*PJ + b*SB + w*SW; the tile width
+// is chosen on the host so that the tile fits the LDS budget.
 // ---------------------------------------------------------------------------
 
-__host__ __device__ constexpr int rc_chunk(int na) {
-    return na % 8 == 0 ? 8 : na % 6 == 0 ? 6 : na % 4 == 0 ? 4 : na % 3 == 0 ? 3 : na;
-}
+__host__ __device__ constexpr int rc_chunk(int na) { return na; }
 
-// The chunk loop stays rolled: the chunk in flight is always a[0..C), and the
-// register array is rotated left by C after each chunk (NA/C rotations bring
-// it back to its original order), so every register index is static.
 template <int NA, class T, class ColFn>
 __device__ __forceinline__ void exchange_axis(cpx<T> (&a)[NA], int w, int b, int SB, int SW,
                                               int PJ, vec2_t<T> *lds, ColFn col) {
-    constexpr int C = rc_chunk(NA);
     vec2_t<T> *mine = lds + b * SB + w * SW;
-#pragma unroll 1
-    for (int c0 = 0; c0 < NA; c0 += C) {
 #pragma unroll
-        for (int j = 0; j < C; ++j) st<T>(mine + j * PJ, a[j]);
-        __syncthreads();
-        col(c0, C);
-        __syncthreads();
-        cpx<T> head[C];
+    for (int j = 0; j < NA; ++j) st<T>(mine + j * PJ, a[j]);
+    __syncthreads();
+    col(0, NA);
+    __syncthreads();
 #pragma unroll
-        for (int j = 0; j < C; ++j) head[j] = ld<T>(mine + j * PJ);
-#pragma unroll
-        for (int i = 0; i < NA - C; ++i) a[i] = a[i + C];
-#pragma unroll
-        for (int j = 0; j < C; ++j) a[NA - C + j] = head[j];
-        __syncthreads();
-    }
+    for (int j = 0; j < NA; ++j) a[j] = ld<T>(mine + j * PJ);
 }
 
 // Column transform forward, times scale(info, position), inverse, in one
@@ -398,12 +384,16 @@ template <class T> zt_plan plan_zt(const geom &g, size_t lds_budget) {
     zt_plan p{};
     const long Lxy = (long)g.Lx * g.Ly;
     if (g.Lt <= 32 && g.Lz <= 32) {
+        auto rc_bytes = [&](int w) {
+            return (size_t)rc_chunk(g.Lt) * ((size_t)g.Lz * w + ZT_PAD) * sizeof(vec2_t<T>);
+        };
         int W = 128 / (int)sizeof(vec2_t<T>);
-        while (W > 1 && (W * g.Lz > rc_max_threads<T>() || W > Lxy)) W >>= 1;
-        if (W * g.Lz <= rc_max_threads<T>()) {
+        while (W > 1 && (W * g.Lz > rc_max_threads<T>() || W > Lxy || rc_bytes(W) > lds_budget))
+            W >>= 1;
+        if (W * g.Lz <= rc_max_threads<T>() && rc_bytes(W) <= 160 * 1024) {
             p.rc = true;
             p.W = W;
-            p.lds = (size_t)rc_chunk(g.Lt) * ((size_t)g.Lz * W + ZT_PAD) * sizeof(vec2_t<T>);
+            p.lds = rc_bytes(W);
             return p;
         }
     }

@@ -32,6 +32,9 @@ struct fin_params {
 struct geom {
     int Lx, Ly, Lz, Lt;
     long V;
+    // site-kernel block order: 0 = linear; > 0 = z planes per XCD slab of the
+    // t-major order (used when Lx*Ly is a multiple of the site block and Lz of 8)
+    int zper = 0;
 };
 
 constexpr int SITE_BLOCK = 256;  // threads per block of the site kernels

@@ -149,8 +149,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
     k_div_reduce(geom g, const vec2_t<T> *__restrict__ L, vec2_t<T> *__restrict__ D,
                  double *__restrict__ partials, const dev_status *__restrict__ status) {
     if (status->done) return;
-    const int b = xcd_block(blockIdx.x, gridDim.x);
-    const long s = (long)b * SITE_BLOCK + threadIdx.x;
+    const long s = block_first_site(g, blockIdx.x, gridDim.x) + threadIdx.x;
     double fs = 0, ts = 0;
     if (s < g.V) {
         const nbr n = neighbours(g, s);
@@ -173,7 +172,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         st<T>(D + 2 * g.V + s, f2);
         st<T>(D + 3 * g.V + s, f3);
     }
-    block_sum2<SITE_BLOCK>(fs, ts, partials, b);
+    block_sum2<SITE_BLOCK>(fs, ts, partials, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -187,8 +186,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
              vec2_t<T> *__restrict__ G, T c, double *__restrict__ partials,
              const dev_status *__restrict__ status) {
     if (status->done) return;
-    const int b = xcd_block(blockIdx.x, gridDim.x);
-    const long s = (long)b * SITE_BLOCK + threadIdx.x;
+    const long s = block_first_site(g, blockIdx.x, gridDim.x) + threadIdx.x;
     double fs = 0, ts = 0;
     if (s < g.V) {
         const nbr n = neighbours(g, s);
@@ -233,7 +231,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
                 }
         }
     }
-    block_sum2<SITE_BLOCK>(fs, ts, partials, b);
+    block_sum2<SITE_BLOCK>(fs, ts, partials, blockIdx.x);
 }
 
 // reorder 4 fields between natural index order and transform-position order

@@ -126,3 +126,32 @@ def test_mixed_iterate_applies_accumulated_transformation(lgf_gpu):
     assert mu < 1e-14
     ref = oracle.iterate(U, ALPHA, 6)
     assert np.max(np.abs(out - ref)) < 1e-4
+
+
+# ------------------------------------------- plain (unaccelerated) steepest descent
+
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (8, 8, 6, 4)])
+def test_plain_steepest_descent_lockstep(lgf_gpu, L):
+    U, _ = inputs.make_config(L, 0.5, 60 + sum(L))
+    for step in range(3):
+        Ug = gpu(U)
+        lgf_gpu.iterate(Ug, ALPHA, 1, accelerate=False)
+        got = cpu(Ug)
+        ref = oracle.fix(U, ALPHA, 0.0, 1, accelerate=False)["U"]
+        assert np.max(np.abs(got - ref)) < 1e-13, step
+        U = got
+
+
+def test_plain_steepest_descent_solve(lgf_gpu):
+    """Converges to the same kind of fixed point but needs many more sweeps
+    than the accelerated method (critical slowing down)."""
+    U, _ = inputs.make_config((8, 8, 8, 8), 0.5, 61)
+    ref = oracle.fix(U, ALPHA, 1e-10, 3000, accelerate=False)
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, ALPHA, 1e-10, max_iter=3000, accelerate=False)
+    assert r.status == 0 and ref["status"] == 0
+    assert abs(r.iterations - ref["iterations"]) <= 1
+    assert abs(r.F - ref["F"]) < 1e-10
+    assert oracle.theta(cpu(Ug)) < 1e-10
+    fa = lgf_gpu.fix(gpu(U), ALPHA, 1e-10, max_iter=3000)
+    assert r.iterations > 2 * fa.iterations

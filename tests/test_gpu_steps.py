@@ -91,7 +91,8 @@ def test_link_storage_round_trip(lgf_gpu):
 
 
 @pytest.mark.parametrize("L", [(4, 4, 4, 4), (8, 8, 8, 8), (4, 6, 8, 12), (2, 3, 4, 6),
-                               (48, 4, 4, 6), (4, 6, 4, 96), (12, 12, 12, 12)])
+                               (48, 4, 4, 6), (4, 6, 4, 96), (12, 12, 12, 12),
+                               (16, 16, 16, 16), (32, 8, 8, 6)])
 def test_lockstep_sweeps(lgf_gpu, L):
     """Feed the GPU state to the oracle, take one sweep on each side, compare
     the links; repeat.  Also checks F and theta reported for the new links."""

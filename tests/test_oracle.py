@@ -303,3 +303,34 @@ def test_theta_gradient_matches_finite_differences():
         fd = (oracle.theta(Up.reshape(U.shape)) - oracle.theta(Um.reshape(U.shape))) / (2 * h)
         errs.append(abs(fd - grad.reshape(4, V, 8)[mu, s, a]))
     assert max(errs) < 1e-7 * np.max(np.abs(grad))
+
+
+# ------------------------------------------------ unaccelerated steepest descent
+
+def test_plain_steepest_descent_mode_contraction():
+    """Without Fourier acceleration a single Abelian plane-wave mode of lattice
+    momentum p contracts by (1 - alpha p2(p)) per sweep, so theta shrinks by
+    (1 - alpha p2)^2: slow for the lowest mode (critical slowing down)."""
+    L = (8, 8, 8, 8)
+    t, z, y, x = np.meshgrid(*[np.arange(n) for n in inputs.site_shape(L)], indexing="ij")
+    amp = 1e-6
+    phase = amp * np.cos(2 * np.pi * x / L[0])  # longitudinal mode k = (1, 0, 0, 0) in A_x
+    U = inputs.unit_config(L)
+    d3 = np.array([1.0, -1.0, 0.0])
+    for i in range(3):
+        U[0, ..., i, i] = np.exp(0.5j * phase * d3[i])
+    p2 = 4 * np.sin(np.pi / L[0]) ** 2
+    for alpha, acc in ((0.08, False), (0.08, True)):
+        r = oracle.fix(U, alpha, 0.0, 3, accelerate=acc)
+        ratios = r["theta_hist"][1:] / r["theta_hist"][:-1]
+        expect = (1 - alpha * p2) ** 2 if not acc else (1 - 16 * alpha) ** 2
+        assert np.all(np.abs(ratios - expect) < 1e-6), (acc, ratios, expect)
+
+
+def test_plain_steepest_descent_converges_slower():
+    U, _ = inputs.make_config((8, 8, 8, 8), 0.5, 51)
+    fa = oracle.fix(U, ALPHA, 1e-10, 2000)
+    sd = oracle.fix(U, ALPHA, 1e-10, 2000, accelerate=False)
+    assert fa["status"] == 0 and sd["status"] == 0
+    assert sd["iterations"] > 2 * fa["iterations"]
+    assert np.all(np.diff(sd["F_hist"]) >= -1e-15)

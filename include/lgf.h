@@ -64,7 +64,7 @@ typedef enum {
     LGF_ERR_OOM = 3,          /* device allocation failed */
     LGF_NOT_CONVERGED = 4,    /* max_iter updates applied, theta >= tol */
     LGF_ERR_NONFINITE = 5,    /* theta became NaN or Inf */
-    LGF_DIVERGING = 6         /* theta rose for 8 consecutive iterations */
+    LGF_DIVERGING = 6         /* theta rose 8 sweeps in a row to over 100x its minimum */
 } lgf_status;
 
 typedef enum {

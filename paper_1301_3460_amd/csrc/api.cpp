@@ -359,7 +359,10 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
     c->g.Lz = L[2];
     c->g.Lt = L[3];
     c->g.V = (long)L[0] * L[1] * L[2] * L[3];
-    c->g.zper = ((long)L[0] * L[1] % SITE_BLOCK == 0 && L[2] % 8 == 0) ? L[2] / 8 : 0;
+    // 64 consecutive xy-sites x 4 t per block where the shape allows it (the
+    // 8x8-tile variant keeps more neighbours in L2 but its short rows cost
+    // more in DRAM efficiency than they save)
+    c->g.tblock = ((long)L[0] * L[1] % 64 == 0 && L[3] % 4 == 0) ? 1 : 0;
     c->precision = precision;
     c->stream = static_cast<hipStream_t>(stream);
     if (hipGetDevice(&c->device) != hipSuccess) {

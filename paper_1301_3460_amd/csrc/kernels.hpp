@@ -9,6 +9,7 @@ namespace lgf {
 // `done` is set.
 struct dev_status {
     double F, theta, theta_prev;
+    double theta_min;  // smallest theta of the phase
     int n;          // gauge updates applied in the current phase
     int done;       // 1: stop (kernels become no-ops)
     int code;       // 0 running, 1 converged, 4 max_iter, 5 non-finite, 6 diverging
@@ -18,7 +19,11 @@ struct dev_status {
 };
 
 enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXITER = 4, ST_NONFINITE = 5, ST_DIVERGING = 6 };
+// Divergence: theta rose DIVERGE_RISES sweeps in a row and exceeds
+// DIVERGE_GROWTH times its smallest value so far (plain steepest descent lets
+// theta rise for a while as F still increases, so rises alone are no test).
 constexpr int DIVERGE_RISES = 8;
+constexpr double DIVERGE_GROWTH = 100.0;
 
 // Stopping test after a sweep kernel: a one-block kernel sums the per-block
 // partials in fixed order and updates the device status (enabled == 0: the
@@ -32,9 +37,9 @@ struct fin_params {
 struct geom {
     int Lx, Ly, Lz, Lt;
     long V;
-    // site-kernel block order: 0 = linear; > 0 = z planes per XCD slab of the
-    // t-major order (used when Lx*Ly is a multiple of the site block and Lz of 8)
-    int zper = 0;
+    // site-kernel tiling (see block_site): 0 consecutive sites; 1 64 xy-sites
+    // x 4 t (Lx*Ly % 64 == 0, Lt % 4 == 0); 2 8x8 xy tile x 4 t (Lx, Ly % 8 == 0)
+    int tblock = 0;
 };
 
 constexpr int SITE_BLOCK = 256;  // threads per block of the site kernels

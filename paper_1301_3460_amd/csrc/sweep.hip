@@ -131,12 +131,13 @@ __device__ __forceinline__ void finalize_state(double A, double B, dev_status *s
         st.code = ST_MAXITER;
     } else {
         st.rises = (st.n > 0 && th > st.theta_prev) ? st.rises + 1 : 0;
-        if (st.rises >= DIVERGE_RISES) {
+        if (st.rises >= DIVERGE_RISES && th > DIVERGE_GROWTH * st.theta_min) {
             st.done = 1;
             st.code = ST_DIVERGING;
         }
     }
     st.theta_prev = th;
+    st.theta_min = (st.n == 0 || th < st.theta_min) ? th : st.theta_min;
     *status = st;
 }
 
@@ -149,7 +150,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
     k_div_reduce(geom g, const vec2_t<T> *__restrict__ L, vec2_t<T> *__restrict__ D,
                  double *__restrict__ partials, const dev_status *__restrict__ status) {
     if (status->done) return;
-    const long s = block_first_site(g, blockIdx.x, gridDim.x) + threadIdx.x;
+    const long s = block_site(g, blockIdx.x, gridDim.x, threadIdx.x);
     double fs = 0, ts = 0;
     if (s < g.V) {
         const nbr n = neighbours(g, s);
@@ -186,7 +187,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
              vec2_t<T> *__restrict__ G, T c, double *__restrict__ partials,
              const dev_status *__restrict__ status) {
     if (status->done) return;
-    const long s = block_first_site(g, blockIdx.x, gridDim.x) + threadIdx.x;
+    const long s = block_site(g, blockIdx.x, gridDim.x, threadIdx.x);
     double fs = 0, ts = 0;
     if (s < g.V) {
         const nbr n = neighbours(g, s);
@@ -268,6 +269,7 @@ __global__ void k_status_reset(dev_status *status, int hist_base) {
     st.F = 0;
     st.theta = 0;
     st.theta_prev = 0;
+    st.theta_min = 0;
     st.n = 0;
     st.done = 0;
     st.code = ST_RUNNING;

@@ -246,7 +246,7 @@ int check_ctx(lgf_ctx *c) {
 
 // Pack caller links into FP64 working buffer 0, then F/theta of them.
 int eval_links64(lgf_ctx *c, const double *U, double &F, double &theta) {
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<double>(c->g, c->L64[0], c->D64[0], c->partials, c->status,
                                         finp(c, false), c->stream));
@@ -265,7 +265,7 @@ int ensure_diff_scratch(lgf_ctx *c) {
             return fail(c, LGF_ERR_OOM, "out of device memory (differentiation scratch)");
     }
     if (!c->Lrot) {
-        if (hipMalloc(&c->Lrot, (size_t)24 * c->g.V * sizeof(double2)) != hipSuccess)
+        if (hipMalloc(&c->Lrot, (size_t)24 * c->g.S * sizeof(double2)) != hipSuccess)
             return fail(c, LGF_ERR_OOM, "out of device memory (differentiation scratch)");
     }
     return LGF_OK;
@@ -285,8 +285,8 @@ template <class T>
 int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
     using P = prec<T>;
     const bool accG = std::is_same<T, float>::value;
-    HIPCHK(c, launch_pack_links<T>(U, P::links(c, 0), c->g.V, c->stream));
-    if (accG) HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->stream));
+    HIPCHK(c, launch_pack_links<T>(U, P::links(c, 0), c->g.V, c->g.S, c->stream));
+    if (accG) HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->g.S, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<T>(c->g, P::links(c, 0), P::field(c, 0), c->partials, c->status,
                                    finp(c, true, 0.0, n + 1, 0), c->stream));
@@ -359,10 +359,15 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
     c->g.Lz = L[2];
     c->g.Lt = L[3];
     c->g.V = (long)L[0] * L[1] * L[2] * L[3];
-    // 64 consecutive xy-sites x 4 t per block where the shape allows it (the
-    // 8x8-tile variant keeps more neighbours in L2 but its short rows cost
-    // more in DRAM efficiency than they save)
+    c->g.S = c->g.V + SOA_PAD;
+    // 64 consecutive xy-sites x 4 t per block where the shape allows it (8x8
+    // xy tiles keep more neighbours in a block, but their short rows cost more
+    // in DRAM efficiency than they save)
     c->g.tblock = ((long)L[0] * L[1] % 64 == 0 && L[3] % 4 == 0) ? 1 : 0;
+    {
+        const long nseg = (long)L[0] * L[1] / 64;
+        c->g.sgroup = (nseg % 4 == 0) ? 4 : (nseg % 2 == 0) ? 2 : 1;
+    }
     c->precision = precision;
     c->stream = static_cast<hipStream_t>(stream);
     if (hipGetDevice(&c->device) != hipSuccess) {
@@ -373,11 +378,12 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
     c->nparts = site_blocks(V);
     auto alloc = [&](void **p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; };
     bool ok = true;
-    ok = ok && alloc((void **)&c->L64[0], (size_t)24 * V * sizeof(double2));
-    ok = ok && alloc((void **)&c->L64[1], (size_t)24 * V * sizeof(double2));
-    ok = ok && alloc((void **)&c->D64[0], (size_t)4 * V * sizeof(double2));
-    ok = ok && alloc((void **)&c->D64[1], (size_t)4 * V * sizeof(double2));
-    if (precision == LGF_MIXED) ok = ok && alloc((void **)&c->G32, (size_t)6 * V * sizeof(float2));
+    const long S = c->g.S;
+    ok = ok && alloc((void **)&c->L64[0], (size_t)24 * S * sizeof(double2));
+    ok = ok && alloc((void **)&c->L64[1], (size_t)24 * S * sizeof(double2));
+    ok = ok && alloc((void **)&c->D64[0], (size_t)4 * S * sizeof(double2));
+    ok = ok && alloc((void **)&c->D64[1], (size_t)4 * S * sizeof(double2));
+    if (precision == LGF_MIXED) ok = ok && alloc((void **)&c->G32, (size_t)6 * S * sizeof(float2));
     ok = ok && alloc((void **)&c->tw64, TW_M * sizeof(double2));
     ok = ok && alloc((void **)&c->tw32, TW_M * sizeof(float2));
     const int nt = L[0] + L[1] + L[2] + L[3];
@@ -396,7 +402,7 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
     }
     // FP32 working links live in the second FP64 buffer (2 x 12 floats per link)
     c->L32[0] = reinterpret_cast<float2 *>(c->L64[1]);
-    c->L32[1] = reinterpret_cast<float2 *>(c->L64[1]) + (size_t)24 * V;
+    c->L32[1] = reinterpret_cast<float2 *>(c->L64[1]) + (size_t)24 * S;
 
     auto tw64 = make_twiddles<double2>();
     auto tw32 = make_twiddles<float2>();
@@ -460,8 +466,8 @@ static int solve(lgf_ctx *c, double *U, double alpha, double tol, int max_iter, 
     int cur64 = 0;
     if (c->precision == LGF_MIXED) {
         // FP32 phase on a downcast copy; G accumulates the applied transformation
-        HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g.V, c->stream));
-        HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->stream));
+        HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g.V, c->g.S, c->stream));
+        HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->g.S, c->stream));
         const double tol32 = std::max(tol, c->theta_switch);
         rc = run_phase<float>(c, alpha, tol32, max_iter, true, 0, st);
         if (rc) return rc;
@@ -477,14 +483,14 @@ static int solve(lgf_ctx *c, double *U, double alpha, double tol, int max_iter, 
             cur64 = n64 & 1;
         }
     } else {
-        HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+        HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
         rc = run_phase<double>(c, alpha, tol, max_iter, false, 0, st);
         if (rc) return rc;
         n64 = st.n;
         code = st.code;
         cur64 = n64 & 1;
     }
-    HIPCHK(c, launch_unpack_links(c->L64[cur64], U, c->g.V, c->stream));
+    HIPCHK(c, launch_unpack_links(c->L64[cur64], U, c->g.V, c->g.S, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->hist_len = n32 + n64 + 1;
     const int out = status_to_code(code);
@@ -523,20 +529,20 @@ int lgf_iterate(lgf_ctx *c, double *U, double alpha, int n_iter, lgf_result *res
     dev_status st{};
     int n32 = 0, n64 = 0, cur64 = 0;
     if (c->precision == LGF_MIXED) {
-        HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g.V, c->stream));
-        HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->stream));
+        HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g.V, c->g.S, c->stream));
+        HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->g.S, c->stream));
         rc = run_phase<float>(c, alpha, 0.0, n_iter, true, 0, st);
         if (rc) return rc;
         n32 = st.n;
         HIPCHK(c, launch_switch(c->g, c->G32, U, c->L64[0], c->stream));
     } else {
-        HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+        HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
         rc = run_phase<double>(c, alpha, 0.0, n_iter, false, 0, st);
         if (rc) return rc;
         n64 = st.n;
         cur64 = n64 & 1;
     }
-    HIPCHK(c, launch_unpack_links(c->L64[cur64], U, c->g.V, c->stream));
+    HIPCHK(c, launch_unpack_links(c->L64[cur64], U, c->g.V, c->g.S, c->stream));
     double F = st.F, th = st.theta;
     if (c->precision == LGF_MIXED) {
         rc = eval_links64(c, U, F, th);
@@ -565,7 +571,7 @@ int lgf_functional(lgf_ctx *c, const double *U, const double *g, double *F) {
         double th;
         return eval_links64(c, U, *F, th);
     }
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
     HIPCHK(c, launch_functional_g(c->g, c->L64[0], g, c->partials, c->stream));
     double A, B;
     rc = sum_partials(c, A, B);
@@ -588,7 +594,7 @@ int lgf_plaquette(lgf_ctx *c, const double *U, double *P) {
     if (!U || !P) return fail(c, LGF_ERR_ARG, "null argument");
     int rc = check_ctx(c);
     if (rc) return rc;
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
     HIPCHK(c, launch_plaquette(c->g, c->L64[0], c->partials, c->stream));
     double A, B;
     rc = sum_partials(c, A, B);
@@ -602,11 +608,11 @@ int lgf_divergence(lgf_ctx *c, const double *U, double *Delta) {
     if (!U || !Delta) return fail(c, LGF_ERR_ARG, "null argument");
     int rc = check_ctx(c);
     if (rc) return rc;
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<double>(c->g, c->L64[0], c->D64[0], c->partials, c->status,
                                         finp(c, false), c->stream));
-    HIPCHK(c, launch_matrix_from_field(c->D64[0], Delta, c->g.V, c->stream));
+    HIPCHK(c, launch_matrix_from_field(c->D64[0], Delta, c->g.V, c->g.S, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LGF_OK;
 }
@@ -617,12 +623,12 @@ int lgf_fourier_accelerate(lgf_ctx *c, const double *D, double *LD) {
     int rc = check_ctx(c);
     if (rc) return rc;
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
-    HIPCHK(c, launch_field_from_matrix(D, c->D64[0], c->g.V, c->stream));
+    HIPCHK(c, launch_field_from_matrix(D, c->D64[0], c->g.V, c->g.S, c->stream));
     HIPCHK(c, launch_fft_xy<double>(c->g, c->D64[0], -1, c->tw64, c->status, c->stream));
     HIPCHK(c, launch_fft_zt<double>(c->g, c->D64[0], 0, c->tw64, c->pt64,
                                     c->p2max / (double)c->g.V, c->zt64, c->status, c->stream));
     HIPCHK(c, launch_fft_xy<double>(c->g, c->D64[0], +1, c->tw64, c->status, c->stream));
-    HIPCHK(c, launch_matrix_from_field(c->D64[0], LD, c->g.V, c->stream));
+    HIPCHK(c, launch_matrix_from_field(c->D64[0], LD, c->g.V, c->g.S, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LGF_OK;
 }
@@ -633,24 +639,26 @@ int lgf_fft4d(lgf_ctx *c, double *fields, int sign) {
     int rc = check_ctx(c);
     if (rc) return rc;
     double2 *F = reinterpret_cast<double2 *>(fields);
+    const long V = c->g.V, S = c->g.S;
+    double2 *W = c->D64[0];
+    const size_t row = (size_t)V * sizeof(double2);
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     if (sign < 0) {
-        HIPCHK(c, launch_fft_xy<double>(c->g, F, -1, c->tw64, c->status, c->stream));
-        HIPCHK(c, launch_fft_zt<double>(c->g, F, -1, c->tw64, c->pt64, 0.0, c->zt64, c->status,
+        // caller layout (stride V) -> work buffer (stride S), transform, natural order back
+        HIPCHK(c, hipMemcpy2DAsync(W, S * sizeof(double2), F, row, row, 4,
+                                   hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, launch_fft_xy<double>(c->g, W, -1, c->tw64, c->status, c->stream));
+        HIPCHK(c, launch_fft_zt<double>(c->g, W, -1, c->tw64, c->pt64, 0.0, c->zt64, c->status,
                                         c->stream));
-        HIPCHK(c, launch_reorder_fields(c->g, F, c->D64[0], 1, c->stream));
+        HIPCHK(c, launch_reorder_fields(c->g, W, S, F, V, 1, c->stream));
     } else {
-        HIPCHK(c, launch_reorder_fields(c->g, F, c->D64[0], 0, c->stream));
-        HIPCHK(c, hipMemcpyAsync(F, c->D64[0], (size_t)4 * c->g.V * sizeof(double2),
-                                 hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, launch_fft_zt<double>(c->g, F, +1, c->tw64, c->pt64, 0.0, c->zt64, c->status,
+        HIPCHK(c, launch_reorder_fields(c->g, F, V, W, S, 0, c->stream));
+        HIPCHK(c, launch_fft_zt<double>(c->g, W, +1, c->tw64, c->pt64, 0.0, c->zt64, c->status,
                                         c->stream));
-        HIPCHK(c, launch_fft_xy<double>(c->g, F, +1, c->tw64, c->status, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        return LGF_OK;
+        HIPCHK(c, launch_fft_xy<double>(c->g, W, +1, c->tw64, c->status, c->stream));
+        HIPCHK(c, hipMemcpy2DAsync(F, row, W, S * sizeof(double2), row, 4,
+                                   hipMemcpyDeviceToDevice, c->stream));
     }
-    HIPCHK(c, hipMemcpyAsync(F, c->D64[0], (size_t)4 * c->g.V * sizeof(double2),
-                             hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LGF_OK;
 }
@@ -673,7 +681,7 @@ int lgf_functional_omega_grad(lgf_ctx *c, const double *U, const double *omega, 
     if (rc) return rc;
     if ((rc = ensure_diff_scratch(c))) return rc;
     HIPCHK(c, launch_expm_sites(omega, c->gaos, c->g.V, c->stream));
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
     HIPCHK(c, launch_rotate_links(c->g, c->L64[0], c->gaos, c->Lrot, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<double>(c->g, c->Lrot, c->D64[0], c->partials, c->status,
@@ -693,11 +701,11 @@ int lgf_theta_grad(lgf_ctx *c, const double *U, const double *eps, double *theta
     int rc = check_ctx(c);
     if (rc) return rc;
     if ((rc = ensure_diff_scratch(c))) return rc;
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
     const void *Lw = c->L64[0];
     if (eps) {
         HIPCHK(c, launch_expm_sites(eps, c->gaos, 4 * c->g.V, c->stream));
-        HIPCHK(c, launch_left_multiply_links(c->L64[0], c->gaos, c->Lrot, c->g.V, c->stream));
+        HIPCHK(c, launch_left_multiply_links(c->L64[0], c->gaos, c->Lrot, c->g.V, c->g.S, c->stream));
         Lw = c->Lrot;
     }
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));

@@ -20,29 +20,23 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // Site of thread tid of site-kernel block b.  Blocks are first remapped so
 // that each XCD walks a contiguous range.
 //   g.tblock == 0: consecutive sites.
-//   g.tblock == 1: the block's four waves take 64 consecutive xy-sites (one
-//     coalesced row each) at 4 consecutive t; blocks advance xy-segment
-//     fastest, then z.
-//   g.tblock == 2: each wave takes an 8x8 xy tile (eight 8-site rows) at one
-//     of 4 consecutive t; blocks advance z fastest, then xy tile, then t.
-// Both tilings keep most x, y and t neighbour pairs inside a block and put
-// the blocks that share the remaining ones next to each other in dispatch
-// order on the same XCD, where the L2 still holds the lines.
+//   g.tblock == 1: the block's four waves take 64 consecutive xy-sites (a
+//     "segment", one coalesced row each) at 4 consecutive t.  Blocks advance
+//     through a group of g.sgroup adjacent segments fastest, then z, then the
+//     segment group, then t: three of four t-neighbour pairs are inside a
+//     block, and the blocks holding the y and z neighbours are at most
+//     g.sgroup positions apart in dispatch order on the same XCD, so their
+//     lines are still in that XCD's L2.
 __device__ __forceinline__ long block_site(const geom &g, int b, int nb, int tid) {
     const int B = xcd_block(b, nb);
     if (!g.tblock) return (long)B * SITE_BLOCK + tid;
-    const int Lxy = g.Lx * g.Ly;
-    if (g.tblock == 1) {
-        const int nseg = Lxy >> 6;
-        const int seg = B % nseg, r = B / nseg;
-        const int z = r % g.Lz, t = (r / g.Lz) * 4 + (tid >> 6);
-        return (long)seg * 64 + (tid & 63) + (long)Lxy * (z + (long)g.Lz * t);
-    }
-    const int ntx = g.Lx >> 3, ntile = ntx * (g.Ly >> 3);
-    const int z = B % g.Lz, r = B / g.Lz;
-    const int tile = r % ntile, t = (r / ntile) * 4 + (tid >> 6);
-    const int x = (tile % ntx) * 8 + (tid & 7), y = (tile / ntx) * 8 + ((tid >> 3) & 7);
-    return (long)x + (long)g.Lx * y + (long)Lxy * (z + (long)g.Lz * t);
+    const int Lxy = g.Lx * g.Ly, G = g.sgroup, ngrp = (Lxy >> 6) / G;
+    const int sg = B % G;
+    int r = B / G;
+    const int z = r % g.Lz;
+    r /= g.Lz;
+    const int seg = (r % ngrp) * G + sg, t = (r / ngrp) * 4 + (tid >> 6);
+    return (long)seg * 64 + (tid & 63) + (long)Lxy * (z + (long)g.Lz * t);
 }
 
 struct nbr {

@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(XY_BLOCK)
     vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
     const int Lx = g.Lx, Ly = g.Ly, P = Lx + 1;
     const long Lxy = (long)Lx * Ly;
-    vec2_t<T> *plane = D + (long)blockIdx.y * g.V + (long)blockIdx.x * Lxy;
+    vec2_t<T> *plane = D + (long)blockIdx.y * g.S + (long)blockIdx.x * Lxy;
     for (int i = threadIdx.x; i < Lxy; i += XY_BLOCK) {
         const int y = i / Lx, x = i - y * Lx;
         lds[y * P + x] = plane[i];
@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(ZT_BLOCK)
     const int PT = Lz * W + ZT_PAD;
     const long s0 = (long)xcd_block(blockIdx.x, gridDim.x) * W;
     const int Wt = (int)min((long)W, Lxy - s0);
-    vec2_t<T> *F = D + (long)blockIdx.y * g.V;
+    vec2_t<T> *F = D + (long)blockIdx.y * g.S;
     const int nel = W * Lz * Lt;
     for (int i = threadIdx.x; i < nel; i += ZT_BLOCK) {
         const int w = i % W, zt = i / W, z = zt % Lz, t = zt / Lz;
@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(rc_max_threads<T>())
     const int x = threadIdx.x % Lx, fl = threadIdx.x / Lx;
     const int f = blockIdx.y * F + fl;
     const int SW = Lx + 1, PJ = F * SW;
-    vec2_t<T> *p = D + (long)f * g.V + (long)blockIdx.x * Lxy + x;
+    vec2_t<T> *p = D + (long)f * g.S + (long)blockIdx.x * Lxy + x;
     cpx<T> a[NY];
 #pragma unroll
     for (int y = 0; y < NY; ++y) a[y] = ld<T>(p + (long)y * Lx);
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(rc_max_threads<T>())
     const int w = threadIdx.x % W, z = threadIdx.x / W;
     const long s0 = (long)xcd_block(blockIdx.x, gridDim.x) * W;
     const bool live = s0 + w < Lxy;
-    vec2_t<T> *p = D + (long)blockIdx.y * g.V + (long)z * Lxy + s0 + w;
+    vec2_t<T> *p = D + (long)blockIdx.y * g.S + (long)z * Lxy + s0 + w;
     const long tstride = (long)Lz * Lxy;
     cpx<T> a[NT];
 #pragma unroll

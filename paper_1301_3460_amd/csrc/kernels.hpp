@@ -34,12 +34,19 @@ struct fin_params {
     double *histF, *histT;
 };
 
+// Component arrays of links and Fourier fields are S = V + SOA_PAD elements
+// apart: an odd number of 128-byte lines (FP32; twice that in FP64) beyond the
+// volume, so the same site's lines in the 28 arrays a sweep kernel streams
+// fall into different L2 sets instead of all into one.
+constexpr long SOA_PAD = 592;
+
 struct geom {
     int Lx, Ly, Lz, Lt;
     long V;
+    long S = 0;  // component stride of the SoA arrays (V + SOA_PAD)
     // site-kernel tiling (see block_site): 0 consecutive sites; 1 64 xy-sites
-    // x 4 t (Lx*Ly % 64 == 0, Lt % 4 == 0); 2 8x8 xy tile x 4 t (Lx, Ly % 8 == 0)
-    int tblock = 0;
+    // x 4 t (needs Lx*Ly % 64 == 0, Lt % 4 == 0), in groups of sgroup segments
+    int tblock = 0, sgroup = 1;
 };
 
 constexpr int SITE_BLOCK = 256;  // threads per block of the site kernels
@@ -47,8 +54,8 @@ inline int site_blocks(long V) { return (int)((V + SITE_BLOCK - 1) / SITE_BLOCK)
 
 // All launchers enqueue on `st` and return hipGetLastError().
 template <class T>
-hipError_t launch_pack_links(const double *Uaos, void *L, long V, hipStream_t st);
-hipError_t launch_unpack_links(const void *L64, double *Uaos, long V, hipStream_t st);
+hipError_t launch_pack_links(const double *Uaos, void *L, long V, long S, hipStream_t st);
+hipError_t launch_unpack_links(const void *L64, double *Uaos, long V, long S, hipStream_t st);
 
 template <class T>
 hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *partials,
@@ -79,21 +86,22 @@ hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const
                          T p2max_over_V, const zt_plan &pl, const dev_status *status,
                          hipStream_t st);
 
-// natural <-> transform-position order of 4 fields (dir -1: positions -> natural)
-hipError_t launch_reorder_fields(const geom &g, const double2 *in, double2 *out, int to_natural,
-                                 hipStream_t st);
+// natural <-> transform-position order of 4 fields with component strides
+// si (input) and so (output); to_natural: positions -> natural order
+hipError_t launch_reorder_fields(const geom &g, const double2 *in, long si, double2 *out, long so,
+                                 int to_natural, hipStream_t st);
 
 hipError_t launch_finalize(const double *partials, int nparts, dev_status *status,
                            const fin_params &fp, hipStream_t st);
 hipError_t launch_status_reset(dev_status *status, int hist_base, hipStream_t st);
 hipError_t launch_reduce_only(const double *partials, int nparts, double *out2, hipStream_t st);
 
-hipError_t launch_g_identity(void *G32, long V, hipStream_t st);
+hipError_t launch_g_identity(void *G32, long V, long S, hipStream_t st);
 hipError_t launch_switch(const geom &g, const void *G32, const double *U0aos, void *L64,
                          hipStream_t st);
 
-hipError_t launch_field_from_matrix(const double *Maos, void *D64, long V, hipStream_t st);
-hipError_t launch_matrix_from_field(const void *D64, double *Maos, long V, hipStream_t st);
+hipError_t launch_field_from_matrix(const double *Maos, void *D64, long V, long S, hipStream_t st);
+hipError_t launch_matrix_from_field(const void *D64, double *Maos, long V, long S, hipStream_t st);
 
 hipError_t launch_plaquette(const geom &g, const void *L64, double *partials, hipStream_t st);
 hipError_t launch_functional_g(const geom &g, const void *L64, const double *gaos,
@@ -104,7 +112,7 @@ hipError_t launch_expm_sites(const double *omega, double *gaos, long n, hipStrea
 hipError_t launch_rotate_links(const geom &g, const void *Lin, const double *gaos, void *Lout,
                                hipStream_t st);
 hipError_t launch_left_multiply_links(const void *Lin, const double *eaos, void *Lout, long V,
-                                      hipStream_t st);
+                                      long S, hipStream_t st);
 hipError_t launch_omega_grad(const geom &g, const void *D64, const double *omega, double *dF,
                              double normF, hipStream_t st);
 hipError_t launch_theta_grad(const geom &g, const void *L64, const void *D64, const double *eps,

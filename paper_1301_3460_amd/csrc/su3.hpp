@@ -23,12 +23,27 @@ template <class T> LGF_HD cpx<T> mk(T r, T i) { return cpx<T>{r, i}; }
 template <class T> LGF_HD cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <class T> LGF_HD cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
 template <class T> LGF_HD cpx<T> operator*(T s, cpx<T> a) { return {s * a.re, s * a.im}; }
+// Complex products are written as explicit fused multiply-add chains: the
+// rounding is then fixed by the source (not by the compiler's contraction
+// choices), and a multiply-accumulate costs four FMAs.
 template <class T> LGF_HD cpx<T> cmul(cpx<T> a, cpx<T> b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
 }
 // a * conj(b)
 template <class T> LGF_HD cpx<T> cmulc(cpx<T> a, cpx<T> b) {
-    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+    return {fma(a.re, b.re, a.im * b.im), fma(a.im, b.re, -a.re * b.im)};
+}
+// acc + a * b
+template <class T> LGF_HD cpx<T> cmac(cpx<T> acc, cpx<T> a, cpx<T> b) {
+    return {fma(a.re, b.re, fma(-a.im, b.im, acc.re)), fma(a.re, b.im, fma(a.im, b.re, acc.im))};
+}
+// acc + a * conj(b)
+template <class T> LGF_HD cpx<T> cmacc(cpx<T> acc, cpx<T> a, cpx<T> b) {
+    return {fma(a.re, b.re, fma(a.im, b.im, acc.re)), fma(a.im, b.re, fma(-a.re, b.im, acc.im))};
+}
+// acc - a * b
+template <class T> LGF_HD cpx<T> cmsub(cpx<T> acc, cpx<T> a, cpx<T> b) {
+    return {fma(-a.re, b.re, fma(a.im, b.im, acc.re)), fma(-a.re, b.im, fma(-a.im, b.re, acc.im))};
 }
 template <class T> LGF_HD cpx<T> conjg(cpx<T> a) { return {a.re, -a.im}; }
 template <class T> LGF_HD T norm2(cpx<T> a) { return a.re * a.re + a.im * a.im; }
@@ -51,25 +66,40 @@ template <class T> struct mat3 {
 
 // row 2 = conj(row0 x row1)
 template <class T> LGF_HD void rebuild_row2(mat3<T> &m) {
-    m.e[2][0] = conjg(cmul(m.e[0][1], m.e[1][2]) - cmul(m.e[0][2], m.e[1][1]));
-    m.e[2][1] = conjg(cmul(m.e[0][2], m.e[1][0]) - cmul(m.e[0][0], m.e[1][2]));
-    m.e[2][2] = conjg(cmul(m.e[0][0], m.e[1][1]) - cmul(m.e[0][1], m.e[1][0]));
+    m.e[2][0] = conjg(cmsub(cmul(m.e[0][1], m.e[1][2]), m.e[0][2], m.e[1][1]));
+    m.e[2][1] = conjg(cmsub(cmul(m.e[0][2], m.e[1][0]), m.e[0][0], m.e[1][2]));
+    m.e[2][2] = conjg(cmsub(cmul(m.e[0][0], m.e[1][1]), m.e[0][1], m.e[1][0]));
+}
+
+// 1/sqrt(x): hardware estimate refined by Newton steps y <- y + y(1 - x y^2)/2
+// (two in FP64, one in FP32), to about 1 ulp.
+LGF_HD double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+LGF_HD float rsqrt_nr(float x) {
+    const float y = __builtin_amdgcn_rsqf(x);
+    const float e = fmaf(-x * y, y, 1.0f);
+    return fmaf(0.5f * y, e, y);
 }
 
 // Gram-Schmidt on rows 0,1 (in place), then rebuild row 2.
 template <class T> LGF_HD void reunitarise(mat3<T> &m) {
     T n0 = norm2(m.e[0][0]) + norm2(m.e[0][1]) + norm2(m.e[0][2]);
-    T r0 = T(1) / sqrt(n0);
+    T r0 = rsqrt_nr(n0);
 #pragma unroll
     for (int j = 0; j < 3; ++j) m.e[0][j] = r0 * m.e[0][j];
     // <row0, row1> = sum conj(row0_j) row1_j
-    cpx<T> ip = mk<T>(0, 0);
+    cpx<T> ip = cmulc(m.e[1][0], m.e[0][0]);
+    ip = cmacc(ip, m.e[1][1], m.e[0][1]);
+    ip = cmacc(ip, m.e[1][2], m.e[0][2]);
 #pragma unroll
-    for (int j = 0; j < 3; ++j) ip = ip + cmulc(m.e[1][j], m.e[0][j]);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) m.e[1][j] = m.e[1][j] - cmul(ip, m.e[0][j]);
+    for (int j = 0; j < 3; ++j) m.e[1][j] = cmsub(m.e[1][j], ip, m.e[0][j]);
     T n1 = norm2(m.e[1][0]) + norm2(m.e[1][1]) + norm2(m.e[1][2]);
-    T r1 = T(1) / sqrt(n1);
+    T r1 = rsqrt_nr(n1);
 #pragma unroll
     for (int j = 0; j < 3; ++j) m.e[1][j] = r1 * m.e[1][j];
     rebuild_row2(m);
@@ -85,16 +115,14 @@ template <class T> LGF_HD mat3<T> mul_abcd(const mat3<T> &A, const mat3<T> &B, c
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             cpx<T> acc = cmul(A.e[i][0], B.e[0][k]);
-            acc = acc + cmul(A.e[i][1], B.e[1][k]);
-            acc = acc + cmul(A.e[i][2], B.e[2][k]);
-            ab[k] = acc;
+            acc = cmac(acc, A.e[i][1], B.e[1][k]);
+            ab[k] = cmac(acc, A.e[i][2], B.e[2][k]);
         }
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             cpx<T> acc = cmulc(ab[0], C.e[j][0]);
-            acc = acc + cmulc(ab[1], C.e[j][1]);
-            acc = acc + cmulc(ab[2], C.e[j][2]);
-            r.e[i][j] = acc;
+            acc = cmacc(acc, ab[1], C.e[j][1]);
+            r.e[i][j] = cmacc(acc, ab[2], C.e[j][2]);
         }
     }
     rebuild_row2(r);
@@ -103,36 +131,34 @@ template <class T> LGF_HD mat3<T> mul_abcd(const mat3<T> &A, const mat3<T> &B, c
 
 // ------------------------------------------------------------------------
 // Storage layouts
-//   links SoA-12:  L[(mu*6 + k)*V + s], k = 3*row + col, row in {0,1}
-//   Fourier field: D[f*V + s], f = 0..3 holding the independent entries of
+//   links SoA-12:  L[(mu*6 + k)*S + s], k = 3*row + col, row in {0,1}
+//   Fourier field: D[f*S + s], f = 0..3 holding the independent entries of
 //                  an anti-hermitian traceless matrix:
 //                  f0 = M01, f1 = M02, f2 = M12,
 //                  f3 = (Im M00) + i (Im M11)
 // ------------------------------------------------------------------------
 
 template <class T>
-LGF_HD mat3<T> load_link(const vec2_t<T> *__restrict__ L, long V, int mu, long s) {
+LGF_HD mat3<T> load_link(const vec2_t<T> *__restrict__ L, long S, int mu, long s) {
     mat3<T> m;
-    const vec2_t<T> *p = L + (long)mu * 6 * V + s;
+    const vec2_t<T> *p = L + (long)mu * 6 * S + s;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) m.e[k / 3][k % 3] = ld<T>(p + (long)k * V);
+    for (int k = 0; k < 6; ++k) m.e[k / 3][k % 3] = ld<T>(p + (long)k * S);
     rebuild_row2(m);
     return m;
 }
 
 template <class T>
-LGF_HD void store_link(vec2_t<T> *__restrict__ L, long V, int mu, long s, const mat3<T> &m) {
-    vec2_t<T> *p = L + (long)mu * 6 * V + s;
+LGF_HD void store_link(vec2_t<T> *__restrict__ L, long S, int mu, long s, const mat3<T> &m) {
+    vec2_t<T> *p = L + (long)mu * 6 * S + s;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) st<T>(p + (long)k * V, m.e[k / 3][k % 3]);
+    for (int k = 0; k < 6; ++k) st<T>(p + (long)k * S, m.e[k / 3][k % 3]);
 }
 
-// g = reunit(1 + c * M) for the anti-hermitian traceless M stored in a
-// Fourier field at site s (c = alpha/2).  Only rows 0,1 of 1 + cM enter.
+// g = reunit(1 + c * M) for the anti-hermitian traceless M whose 4 Fourier-
+// field entries are f (c = alpha/2).  Only rows 0,1 of 1 + cM enter.
 template <class T>
-LGF_HD mat3<T> gauge_from_field(const vec2_t<T> *__restrict__ D, long V, long s, T c) {
-    cpx<T> f0 = ld<T>(D + s), f1 = ld<T>(D + V + s), f2 = ld<T>(D + 2 * V + s),
-           f3 = ld<T>(D + 3 * V + s);
+LGF_HD mat3<T> gauge_from_entries(cpx<T> f0, cpx<T> f1, cpx<T> f2, cpx<T> f3, T c) {
     mat3<T> g;
     g.e[0][0] = mk<T>(1, c * f3.re);
     g.e[0][1] = c * f0;
@@ -142,6 +168,13 @@ LGF_HD mat3<T> gauge_from_field(const vec2_t<T> *__restrict__ D, long V, long s,
     g.e[1][2] = c * f2;
     reunitarise(g);
     return g;
+}
+
+// The same from a Fourier field at site s.
+template <class T>
+LGF_HD mat3<T> gauge_from_field(const vec2_t<T> *__restrict__ D, long S, long s, T c) {
+    return gauge_from_entries<T>(ld<T>(D + s), ld<T>(D + S + s), ld<T>(D + 2 * S + s),
+                                 ld<T>(D + 3 * S + s), c);
 }
 
 // Accumulator of X = sum_mu [U_mu(x-mu) - U_mu(x)] restricted to what the

@@ -23,7 +23,7 @@ namespace lgf {
 // complex128 [4][V][3][3] -> SoA-12 of type T (rows 0,1)
 template <class T>
 __global__ void __launch_bounds__(256) k_pack_links(const double2 *__restrict__ U,
-                                                    vec2_t<T> *__restrict__ L, long V) {
+                                                    vec2_t<T> *__restrict__ L, long V, long S) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 4 * V) return;
     const int mu = (int)(i / V);
@@ -35,37 +35,39 @@ __global__ void __launch_bounds__(256) k_pack_links(const double2 *__restrict__ 
         vec2_t<T> w;
         w.x = (T)v.x;
         w.y = (T)v.y;
-        L[((long)mu * 6 + k) * V + s] = w;
+        L[((long)mu * 6 + k) * S + s] = w;
     }
 }
 
 __global__ void __launch_bounds__(256) k_unpack_links(const double2 *__restrict__ L,
-                                                      double2 *__restrict__ U, long V) {
+                                                      double2 *__restrict__ U, long V, long S) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 4 * V) return;
     const int mu = (int)(i / V);
     const long s = i - (long)mu * V;
-    mat3<double> m = load_link<double>(L, V, mu, s);
+    mat3<double> m = load_link<double>(L, S, mu, s);
     double2 *u = U + i * 9;
 #pragma unroll
     for (int k = 0; k < 9; ++k) u[k] = make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
 }
 
 // anti-hermitian traceless matrix field (AoS 3x3 complex128) <-> 4 Fourier fields
-__global__ void k_field_from_matrix(const double2 *__restrict__ M, double2 *__restrict__ D, long V) {
+__global__ void k_field_from_matrix(const double2 *__restrict__ M, double2 *__restrict__ D, long V,
+                                    long S) {
     const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
     const double2 *m = M + s * 9;
     D[s] = m[1];
-    D[V + s] = m[2];
-    D[2 * V + s] = m[5];
-    D[3 * V + s] = make_double2(m[0].y, m[4].y);
+    D[S + s] = m[2];
+    D[2 * S + s] = m[5];
+    D[3 * S + s] = make_double2(m[0].y, m[4].y);
 }
 
-__global__ void k_matrix_from_field(const double2 *__restrict__ D, double2 *__restrict__ M, long V) {
+__global__ void k_matrix_from_field(const double2 *__restrict__ D, double2 *__restrict__ M, long V,
+                                    long S) {
     const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
-    const double2 f0 = D[s], f1 = D[V + s], f2 = D[2 * V + s], f3 = D[3 * V + s];
+    const double2 f0 = D[s], f1 = D[S + s], f2 = D[2 * S + s], f3 = D[3 * S + s];
     double2 *m = M + s * 9;
     m[0] = make_double2(0.0, f3.x);
     m[1] = f0;
@@ -159,19 +161,19 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         T tr = 0;
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
-            mat3<T> u = load_link<T>(L, g.V, mu, s);
+            mat3<T> u = load_link<T>(L, g.S, mu, s);
             tr += retrace(u);
             xacc_add(X, u, T(-1));
-            mat3<T> um = load_link<T>(L, g.V, mu, n.m[mu]);
+            mat3<T> um = load_link<T>(L, g.S, mu, n.m[mu]);
             xacc_add(X, um, T(1));
         }
         cpx<T> f0, f1, f2, f3;
         ts = (double)delta_pack(X, f0, f1, f2, f3);
         fs = (double)tr;
         st<T>(D + s, f0);
-        st<T>(D + g.V + s, f1);
-        st<T>(D + 2 * g.V + s, f2);
-        st<T>(D + 3 * g.V + s, f3);
+        st<T>(D + g.S + s, f1);
+        st<T>(D + 2 * g.S + s, f2);
+        st<T>(D + 3 * g.S + s, f3);
     }
     block_sum2<SITE_BLOCK>(fs, ts, partials, blockIdx.x);
 }
@@ -191,44 +193,74 @@ __global__ void __launch_bounds__(SITE_BLOCK)
     double fs = 0, ts = 0;
     if (s < g.V) {
         const nbr n = neighbours(g, s);
-        const mat3<T> g0 = gauge_from_field<T>(LD, g.V, s, c);
+        // Eight half-steps h = 2 mu + b: b = 0 transforms the link U_mu(x)
+        // with g(x+mu), b = 1 the link U_mu(x-mu) with g(x-mu).  Each needs 10
+        // loads (4 field entries, 6 link entries); the loads of half-step h+1
+        // are issued before half-step h is computed (software pipelining),
+        // so every wave keeps the next memory round trip in flight.
+        struct half {
+            cpx<T> f[4], u[6];
+        };
+        auto fetch = [&](int h, half &d) {
+            const int mu = h >> 1;
+            const long sf = (h & 1) ? n.m[mu] : n.p[mu];
+            const long sl = (h & 1) ? n.m[mu] : s;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) d.f[f] = ld<T>(LD + (long)f * g.S + sf);
+            const vec2_t<T> *lp = Lin + (long)mu * 6 * g.S + sl;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) d.u[k] = ld<T>(lp + (long)k * g.S);
+        };
+        half d[2];
+        cpx<T> own[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) own[f] = ld<T>(LD + (long)f * g.S + s);
+        fetch(0, d[0]);
+        const mat3<T> g0 = gauge_from_entries<T>(own[0], own[1], own[2], own[3], c);
         xacc<T> X;
         xacc_zero(X);
         T tr = 0;
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            const mat3<T> gp = gauge_from_field<T>(LD, g.V, n.p[mu], c);
-            const mat3<T> u = load_link<T>(Lin, g.V, mu, s);
-            const mat3<T> un = mul_abcd(g0, u, gp);
-            store_link<T>(Lout, g.V, mu, s, un);
-            tr += retrace(un);
-            xacc_add(X, un, T(-1));
-            const mat3<T> gm = gauge_from_field<T>(LD, g.V, n.m[mu], c);
-            const mat3<T> um = load_link<T>(Lin, g.V, mu, n.m[mu]);
-            const mat3<T> umn = mul_abcd(gm, um, g0);
-            xacc_add(X, umn, T(1));
+        for (int h = 0; h < 8; ++h) {
+            if (h < 7) fetch(h + 1, d[(h + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+            const half &cur = d[h & 1];
+            const mat3<T> gn = gauge_from_entries<T>(cur.f[0], cur.f[1], cur.f[2], cur.f[3], c);
+            mat3<T> u;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) u.e[k / 3][k % 3] = cur.u[k];
+            rebuild_row2(u);
+            if ((h & 1) == 0) {
+                const mat3<T> un = mul_abcd(g0, u, gn);  // g(x) U_mu(x) g(x+mu)^+
+                store_link<T>(Lout, g.S, h >> 1, s, un);
+                tr += retrace(un);
+                xacc_add(X, un, T(-1));
+            } else {
+                const mat3<T> umn = mul_abcd(gn, u, g0);  // g(x-mu) U_mu(x-mu) g(x)^+
+                xacc_add(X, umn, T(1));
+            }
         }
         cpx<T> f0, f1, f2, f3;
         ts = (double)delta_pack(X, f0, f1, f2, f3);
         fs = (double)tr;
         st<T>(Dout + s, f0);
-        st<T>(Dout + g.V + s, f1);
-        st<T>(Dout + 2 * g.V + s, f2);
-        st<T>(Dout + 3 * g.V + s, f3);
+        st<T>(Dout + g.S + s, f1);
+        st<T>(Dout + 2 * g.S + s, f2);
+        st<T>(Dout + 3 * g.S + s, f3);
         if constexpr (ACC_G) {
             // G(x) <- g(x) G(x), rows 0,1 kept (12 reals)
             mat3<T> G0;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) G0.e[k / 3][k % 3] = ld<T>(G + (long)k * g.V + s);
+            for (int k = 0; k < 6; ++k) G0.e[k / 3][k % 3] = ld<T>(G + (long)k * g.S + s);
             rebuild_row2(G0);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
                     cpx<T> acc = cmul(g0.e[i][0], G0.e[0][j]);
-                    acc = acc + cmul(g0.e[i][1], G0.e[1][j]);
-                    acc = acc + cmul(g0.e[i][2], G0.e[2][j]);
-                    st<T>(G + (long)(3 * i + j) * g.V + s, acc);
+                    acc = cmac(acc, g0.e[i][1], G0.e[1][j]);
+                    acc = cmac(acc, g0.e[i][2], G0.e[2][j]);
+                    st<T>(G + (long)(3 * i + j) * g.S + s, acc);
                 }
         }
     }
@@ -236,8 +268,8 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 }
 
 // reorder 4 fields between natural index order and transform-position order
-__global__ void k_reorder(geom g, const double2 *__restrict__ in, double2 *__restrict__ out,
-                          int to_natural) {
+__global__ void k_reorder(geom g, const double2 *__restrict__ in, long si, double2 *__restrict__ out,
+                          long so, int to_natural) {
     const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.V) return;
     long r = s;
@@ -250,8 +282,8 @@ __global__ void k_reorder(geom g, const double2 *__restrict__ in, double2 *__res
               f2 = fft_freq_of_pos(g.Lz, a2), f3 = fft_freq_of_pos(g.Lt, a3);
     const long sn = f0 + (long)g.Lx * (f1 + (long)g.Ly * (f2 + (long)g.Lz * f3));
     for (int f = 0; f < 4; ++f) {
-        if (to_natural) out[f * g.V + sn] = in[f * g.V + s];
-        else out[f * g.V + s] = in[f * g.V + sn];
+        if (to_natural) out[f * so + sn] = in[f * si + s];
+        else out[f * so + s] = in[f * si + sn];
     }
 }
 
@@ -293,18 +325,18 @@ __global__ void __launch_bounds__(FIN_BLOCK)
 // mixed precision: accumulated transformation and the hand-over to FP64
 // ---------------------------------------------------------------------------
 
-__global__ void k_g_identity(float2 *__restrict__ G, long V) {
+__global__ void k_g_identity(float2 *__restrict__ G, long V, long S) {
     const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) G[(long)k * V + s] = make_float2(k == 0 || k == 4 ? 1.f : 0.f, 0.f);
+    for (int k = 0; k < 6; ++k) G[(long)k * S + s] = make_float2(k == 0 || k == 4 ? 1.f : 0.f, 0.f);
 }
 
-__device__ __forceinline__ mat3<double> load_G_fp64(const float2 *__restrict__ G, long V, long s) {
+__device__ __forceinline__ mat3<double> load_G_fp64(const float2 *__restrict__ G, long S, long s) {
     mat3<double> m;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        float2 v = G[(long)k * V + s];
+        float2 v = G[(long)k * S + s];
         m.e[k / 3][k % 3] = mk<double>(v.x, v.y);
     }
     reunitarise(m);
@@ -318,16 +350,16 @@ __global__ void __launch_bounds__(SITE_BLOCK)
     const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.V) return;
     const nbr n = neighbours(g, s);
-    const mat3<double> g0 = load_G_fp64(G, g.V, s);
+    const mat3<double> g0 = load_G_fp64(G, g.S, s);
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-        const mat3<double> gp = load_G_fp64(G, g.V, n.p[mu]);
+        const mat3<double> gp = load_G_fp64(G, g.S, n.p[mu]);
         mat3<double> u;
         const double2 *p = U0 + ((long)mu * g.V + s) * 9;
 #pragma unroll
         for (int k = 0; k < 6; ++k) u.e[k / 3][k % 3] = mk<double>(p[k].x, p[k].y);
         rebuild_row2(u);
-        store_link<double>(L, g.V, mu, s, mul_abcd(g0, u, gp));
+        store_link<double>(L, g.S, mu, s, mul_abcd(g0, u, gp));
     }
 }
 
@@ -343,12 +375,12 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         const nbr n = neighbours(g, s);
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
-            const mat3<double> umu = load_link<double>(L, g.V, mu, s);
+            const mat3<double> umu = load_link<double>(L, g.S, mu, s);
 #pragma unroll
             for (int nu = mu + 1; nu < 4; ++nu) {
-                const mat3<double> a = load_link<double>(L, g.V, nu, n.p[mu]);   // U_nu(x+mu)
-                const mat3<double> b = load_link<double>(L, g.V, mu, n.p[nu]);   // U_mu(x+nu)
-                const mat3<double> c = load_link<double>(L, g.V, nu, s);         // U_nu(x)
+                const mat3<double> a = load_link<double>(L, g.S, nu, n.p[mu]);   // U_nu(x+mu)
+                const mat3<double> b = load_link<double>(L, g.S, mu, n.p[nu]);   // U_mu(x+nu)
+                const mat3<double> c = load_link<double>(L, g.S, nu, s);         // U_nu(x)
                 // Re Tr[umu a b^+ c^+] = Re Tr[P Q^+] = Re sum_ij P_ij conj(Q_ij),
                 // P = umu a, Q = c b
                 for (int i = 0; i < 3; ++i)
@@ -380,7 +412,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
             mat3<double> gp;
             const long sp = n.p[mu];
             for (int k = 0; k < 9; ++k) gp.e[k / 3][k % 3] = mk<double>(ga[sp * 9 + k].x, ga[sp * 9 + k].y);
-            const mat3<double> u = load_link<double>(L, g.V, mu, s);
+            const mat3<double> u = load_link<double>(L, g.S, mu, s);
             // Re Tr[g0 u gp^+] = Re sum_ij (g0 u)_ij conj(gp_ij)
             for (int i = 0; i < 3; ++i)
                 for (int j = 0; j < 3; ++j) {
@@ -484,22 +516,22 @@ __global__ void __launch_bounds__(SITE_BLOCK)
     const mat3<double> g0 = load_full(ga, s);
     for (int mu = 0; mu < 4; ++mu) {
         const mat3<double> gp = load_full(ga, n.p[mu]);
-        const mat3<double> u = load_link<double>(Lin, g.V, mu, s);
-        store_link<double>(Lout, g.V, mu, s, mul_abcd(g0, u, gp));
+        const mat3<double> u = load_link<double>(Lin, g.S, mu, s);
+        store_link<double>(Lout, g.S, mu, s, mul_abcd(g0, u, gp));
     }
 }
 
 // Lout_mu(x) = E_mu(x) Lin_mu(x), E full AoS [4][V]
 __global__ void k_left_multiply(const double2 *__restrict__ Lin, const double2 *__restrict__ E,
-                                double2 *__restrict__ Lout, long V) {
+                                double2 *__restrict__ Lout, long V, long S) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 4 * V) return;
     const int mu = (int)(i / V);
     const long s = i - (long)mu * V;
     const mat3<double> e = load_full(E, i);
-    const mat3<double> u = load_link<double>(Lin, V, mu, s);
+    const mat3<double> u = load_link<double>(Lin, S, mu, s);
     mat3<double> r = mat_mul_full(e, u);
-    store_link<double>(Lout, V, mu, s, r);
+    store_link<double>(Lout, S, mu, s, r);
 }
 
 // Im Tr[lambda_a W], a = 0..7
@@ -565,7 +597,7 @@ __global__ void k_omega_grad(geom g, const double2 *__restrict__ D, const double
                              double *__restrict__ dF, double normF) {
     const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.V) return;
-    const double2 f0 = D[s], f1 = D[g.V + s], f2 = D[2 * g.V + s], f3 = D[3 * g.V + s];
+    const double2 f0 = D[s], f1 = D[g.S + s], f2 = D[2 * g.S + s], f3 = D[3 * g.S + s];
     mat3<double> M;
     M.e[0][0] = mk<double>(0, f3.x);
     M.e[0][1] = mk<double>(f0.x, f0.y);
@@ -593,7 +625,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
     if (s >= g.V) return;
     const nbr n = neighbours(g, s);
     auto fieldmat = [&](long q) {
-        const double2 f0 = D[q], f1 = D[g.V + q], f2 = D[2 * g.V + q], f3 = D[3 * g.V + q];
+        const double2 f0 = D[q], f1 = D[g.S + q], f2 = D[2 * g.S + q], f3 = D[3 * g.S + q];
         mat3<double> M;
         M.e[0][0] = mk<double>(0, f3.x);
         M.e[0][1] = mk<double>(f0.x, f0.y);
@@ -612,7 +644,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         mat3<double> Dd;
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) Dd.e[i][j] = dp.e[i][j] - d0.e[i][j];
-        const mat3<double> u = load_link<double>(L, g.V, mu, s);
+        const mat3<double> u = load_link<double>(L, g.S, mu, s);
         mat3<double> ud;
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) ud.e[i][j] = conjg(u.e[j][i]);
@@ -642,17 +674,17 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <class T>
-hipError_t launch_pack_links(const double *Uaos, void *L, long V, hipStream_t st) {
+hipError_t launch_pack_links(const double *Uaos, void *L, long V, long S, hipStream_t st) {
     k_pack_links<T><<<nblk(4 * V, 256), 256, 0, st>>>(reinterpret_cast<const double2 *>(Uaos),
-                                                      static_cast<vec2_t<T> *>(L), V);
+                                                      static_cast<vec2_t<T> *>(L), V, S);
     return hipGetLastError();
 }
-template hipError_t launch_pack_links<double>(const double *, void *, long, hipStream_t);
-template hipError_t launch_pack_links<float>(const double *, void *, long, hipStream_t);
+template hipError_t launch_pack_links<double>(const double *, void *, long, long, hipStream_t);
+template hipError_t launch_pack_links<float>(const double *, void *, long, long, hipStream_t);
 
-hipError_t launch_unpack_links(const void *L64, double *Uaos, long V, hipStream_t st) {
+hipError_t launch_unpack_links(const void *L64, double *Uaos, long V, long S, hipStream_t st) {
     k_unpack_links<<<nblk(4 * V, 256), 256, 0, st>>>(static_cast<const double2 *>(L64),
-                                                     reinterpret_cast<double2 *>(Uaos), V);
+                                                     reinterpret_cast<double2 *>(Uaos), V, S);
     return hipGetLastError();
 }
 
@@ -693,9 +725,9 @@ template hipError_t launch_update<float>(const geom &, const void *, void *, con
                                          void *, float, double *, dev_status *, const fin_params &,
                                          hipStream_t);
 
-hipError_t launch_reorder_fields(const geom &g, const double2 *in, double2 *out, int to_natural,
-                                 hipStream_t st) {
-    k_reorder<<<nblk(g.V, 256), 256, 0, st>>>(g, in, out, to_natural);
+hipError_t launch_reorder_fields(const geom &g, const double2 *in, long si, double2 *out, long so,
+                                 int to_natural, hipStream_t st) {
+    k_reorder<<<nblk(g.V, 256), 256, 0, st>>>(g, in, si, out, so, to_natural);
     return hipGetLastError();
 }
 
@@ -715,8 +747,8 @@ hipError_t launch_reduce_only(const double *partials, int nparts, double *out2, 
     return hipGetLastError();
 }
 
-hipError_t launch_g_identity(void *G32, long V, hipStream_t st) {
-    k_g_identity<<<nblk(V, 256), 256, 0, st>>>(static_cast<float2 *>(G32), V);
+hipError_t launch_g_identity(void *G32, long V, long S, hipStream_t st) {
+    k_g_identity<<<nblk(V, 256), 256, 0, st>>>(static_cast<float2 *>(G32), V, S);
     return hipGetLastError();
 }
 
@@ -728,15 +760,15 @@ hipError_t launch_switch(const geom &g, const void *G32, const double *U0aos, vo
     return hipGetLastError();
 }
 
-hipError_t launch_field_from_matrix(const double *Maos, void *D64, long V, hipStream_t st) {
+hipError_t launch_field_from_matrix(const double *Maos, void *D64, long V, long S, hipStream_t st) {
     k_field_from_matrix<<<nblk(V, 256), 256, 0, st>>>(reinterpret_cast<const double2 *>(Maos),
-                                                      static_cast<double2 *>(D64), V);
+                                                      static_cast<double2 *>(D64), V, S);
     return hipGetLastError();
 }
 
-hipError_t launch_matrix_from_field(const void *D64, double *Maos, long V, hipStream_t st) {
+hipError_t launch_matrix_from_field(const void *D64, double *Maos, long V, long S, hipStream_t st) {
     k_matrix_from_field<<<nblk(V, 256), 256, 0, st>>>(static_cast<const double2 *>(D64),
-                                                      reinterpret_cast<double2 *>(Maos), V);
+                                                      reinterpret_cast<double2 *>(Maos), V, S);
     return hipGetLastError();
 }
 
@@ -767,10 +799,10 @@ hipError_t launch_rotate_links(const geom &g, const void *Lin, const double *gao
 }
 
 hipError_t launch_left_multiply_links(const void *Lin, const double *eaos, void *Lout, long V,
-                                      hipStream_t st) {
+                                      long S, hipStream_t st) {
     k_left_multiply<<<nblk(4 * V, 256), 256, 0, st>>>(static_cast<const double2 *>(Lin),
                                                       reinterpret_cast<const double2 *>(eaos),
-                                                      static_cast<double2 *>(Lout), V);
+                                                      static_cast<double2 *>(Lout), V, S);
     return hipGetLastError();
 }
 

@@ -189,11 +189,13 @@ def iterate(U, alpha: float, n: int) -> np.ndarray:
 
 
 def fix(U, alpha: float = 0.08, tol: float = 1e-15, max_iter: int = 10000,
-        accelerate: bool = True):
+        accelerate: bool = True, exact_exp: bool = False):
     """Gauge fixing to theta < tol.  Returns a dict with the links, the number
     of updates, F and theta of the returned links, their per-iteration
     histories and a status (0 converged, 1 max_iter, 2 non-finite).
-    accelerate=False: plain steepest descent (no Fourier acceleration)."""
+    accelerate=False: plain steepest descent (no Fourier acceleration).
+    exact_exp=True: g = exp((alpha/2) L Delta) exactly, instead of the first-
+    order step followed by reunitarisation."""
     U = _z(U).copy()
     it = ctypes.c_int(0)
     f = ctypes.c_double(0)
@@ -201,7 +203,7 @@ def fix(U, alpha: float = 0.08, tol: float = 1e-15, max_iter: int = 10000,
     Fh = np.zeros(max_iter + 1)
     Th = np.zeros(max_iter + 1)
     st = _load().orc_fix_ex(_L_of_links(U), U, float(alpha), float(tol), int(max_iter),
-                            1 if accelerate else 0, ctypes.byref(it), ctypes.byref(f),
+                            (1 if accelerate else 0) | (2 if exact_exp else 0), ctypes.byref(it), ctypes.byref(f),
                             ctypes.byref(th), Fh, Th)
     n = it.value
     return {"U": U, "iterations": n, "F": f.value, "theta": th.value,

@@ -22,6 +22,10 @@
  *   forward transform unnormalised, inverse with 1/V;
  *   then U_mu(x) <- g(x) U_mu(x) g(x+mu)^dagger for every link at once.
  *   reunit: Gram-Schmidt on rows 0 and 1, row 2 = conj(row0 x row1).
+ * Variants of the step (orc_fix_ex flags): plain steepest descent (Delta in
+ * place of the accelerated field) and the exact exponential
+ * g = exp((alpha/2) * IFFT[K * FFT[Delta]]) (Taylor series with scaling and
+ * squaring on the full 3x3 matrix).
  */
 #include <complex.h>
 #include <math.h>
@@ -443,20 +447,30 @@ int orc_iterate(const int *L, cplx *U, double alpha, int n) {
  * F_hist/theta_hist (may be NULL) receive F_n, theta_n for n = 0..*iters.
  * Returns 0 if converged, 1 if max_iter was reached, 2 on non-finite theta.
  */
-int orc_fix_ex(const int *L, cplx *U, double alpha, double tol, int max_iter, int accelerate,
+#define ORC_ACCELERATE 1 /* Fourier acceleration (else plain steepest descent) */
+#define ORC_EXACT_EXP 2  /* g = exp((alpha/2) L Delta) instead of reunit(1 + ...) */
+
+static void mat_exp(const cplx *X, cplx *E);
+
+int orc_fix_ex(const int *L, cplx *U, double alpha, double tol, int max_iter, int flags,
                int *iters, double *F, double *theta, double *F_hist, double *theta_hist);
 
 int orc_fix(const int *L, cplx *U, double alpha, double tol, int max_iter,
             int *iters, double *F, double *theta, double *F_hist, double *theta_hist) {
-    return orc_fix_ex(L, U, alpha, tol, max_iter, 1, iters, F, theta, F_hist, theta_hist);
+    return orc_fix_ex(L, U, alpha, tol, max_iter, ORC_ACCELERATE, iters, F, theta, F_hist,
+                      theta_hist);
 }
 
 /*
- * As orc_fix; accelerate == 0 gives plain steepest descent (the method before
- * Fourier acceleration): g = reunit(1 + (alpha/2) Delta), no transform.
+ * As orc_fix, with the variants of the update step chosen by flags:
+ *   without ORC_ACCELERATE: plain steepest descent (the method before Fourier
+ *     acceleration), the step is built from Delta itself, no transform;
+ *   with ORC_EXACT_EXP: the step matrix (alpha/2) L Delta is exponentiated
+ *     exactly (mat_exp) instead of to first order plus reunitarisation.
  */
-int orc_fix_ex(const int *L, cplx *U, double alpha, double tol, int max_iter, int accelerate,
+int orc_fix_ex(const int *L, cplx *U, double alpha, double tol, int max_iter, int flags,
                int *iters, double *F, double *theta, double *F_hist, double *theta_hist) {
+    const int accelerate = flags & ORC_ACCELERATE, exact = flags & ORC_EXACT_EXP;
     const int64_t V = volume(L);
     cplx *D = malloc(sizeof(cplx) * 9 * V);
     cplx *LD = malloc(sizeof(cplx) * 9 * V);
@@ -481,8 +495,12 @@ int orc_fix_ex(const int *L, cplx *U, double alpha, double tol, int max_iter, in
         for (int64_t s = 0; s < V; ++s) {
             cplx M[9];
             for (int k = 0; k < 9; ++k) M[k] = 0.5 * alpha * LD[s * 9 + k];
-            M[0] += 1; M[4] += 1; M[8] += 1;
-            reunit(M, g + s * 9);
+            if (exact) {
+                mat_exp(M, g + s * 9);
+            } else {
+                M[0] += 1; M[4] += 1; M[8] += 1;
+                reunit(M, g + s * 9);
+            }
         }
         orc_gauge_rotate(L, U, g);
         ++n;

@@ -334,3 +334,61 @@ def test_plain_steepest_descent_converges_slower():
     assert fa["status"] == 0 and sd["status"] == 0
     assert sd["iterations"] > 2 * fa["iterations"]
     assert np.all(np.diff(sd["F_hist"]) >= -1e-15)
+
+
+# ------------------------------------------------------- exact exponential step
+
+def test_exact_exp_step_matches_scipy():
+    """One exact-exponential step is the gauge rotation by scipy's expm of
+    (alpha/2) L Delta, with L Delta from the pinned transform."""
+    U, _ = inputs.make_config((4, 6, 4, 8), 0.5, 52)
+    LD = oracle.fourier_accelerate(oracle.delta(U))
+    g = np.array([scipy.linalg.expm(0.5 * ALPHA * m) for m in LD.reshape(-1, 3, 3)])
+    ref = oracle.gauge_rotate(U, g.reshape(LD.shape))
+    got = oracle.fix(U, ALPHA, 0.0, 1, exact_exp=True)["U"]
+    assert np.max(np.abs(got - ref)) < 1e-14
+    first_order = oracle.fix(U, ALPHA, 0.0, 1)["U"]
+    assert np.max(np.abs(first_order - ref)) > 1e-6
+
+
+def test_exact_exp_abelian_phases():
+    """On diagonal (Cartan) links all matrices commute and L Delta is diagonal,
+    i*phi_k(x): the exact step adds c (phi_k(x) - phi_k(x+mu)) to the phase of
+    each diagonal entry (c = alpha/2).  The first-order step rotates the
+    first two by psi_k = atan(c phi_k) instead, and the third by
+    -(psi_0 + psi_1), since row 2 is rebuilt from rows 0 and 1."""
+    L = (4, 4, 6, 8)
+    U = inputs.abelian_config(L, 0.3, 53)
+    LD = oracle.fourier_accelerate(oracle.delta(U))
+    phi = np.imag(np.diagonal(LD, axis1=-2, axis2=-1))
+    c = 0.5 * ALPHA
+    got = oracle.fix(U, ALPHA, 0.0, 1, exact_exp=True)["U"]
+    fo = oracle.fix(U, ALPHA, 0.0, 1)["U"]
+    for mu in range(4):
+        phi_p = np.roll(phi, -1, axis=3 - mu)  # phi(x + mu); axes are (t, z, y, x)
+        base = np.angle(np.diagonal(U[mu], axis1=-2, axis2=-1))
+        expect = np.exp(1j * (base + c * (phi - phi_p)))
+        assert np.max(np.abs(np.diagonal(got[mu], axis1=-2, axis2=-1) - expect)) < 1e-14
+        off = got[mu] * (1 - np.eye(3))
+        assert np.max(np.abs(off)) < 1e-15
+        psi = np.arctan(c * phi)
+        psi[..., 2] = -(psi[..., 0] + psi[..., 1])
+        psi_p = np.roll(psi, -1, axis=3 - mu)
+        first = np.exp(1j * (base + psi - psi_p))
+        assert np.max(np.abs(np.diagonal(fo[mu], axis1=-2, axis2=-1) - first)) < 1e-14
+    assert np.max(np.abs(got - fo)) > 1e-6
+
+
+def test_exact_exp_reaches_the_same_maximum():
+    """The two step rules share their fixed points; from the same start they
+    reach the same local maximum of F in about the same number of sweeps."""
+    U, _ = inputs.make_config((8, 8, 8, 8), 0.5, 54)
+    fo = oracle.fix(U, ALPHA, 1e-13, 500)
+    ex = oracle.fix(U, ALPHA, 1e-13, 500, exact_exp=True)
+    assert fo["status"] == 0 and ex["status"] == 0
+    assert abs(fo["iterations"] - ex["iterations"]) <= 2
+    assert abs(fo["F"] - ex["F"]) < 1e-12
+    assert np.all(np.diff(ex["F_hist"]) >= -1e-15)
+    assert abs(oracle.plaquette(ex["U"]) - oracle.plaquette(U)) < 1e-12
+    mu, md = oracle.unitarity(ex["U"])
+    assert mu < 1e-13 and md < 1e-13

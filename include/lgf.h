@@ -98,6 +98,15 @@ int lgf_set_theta_switch(lgf_ctx *ctx, double theta_switch);
  * paragraph after the display equation). */
 int lgf_set_acceleration(lgf_ctx *ctx, int on);
 
+/* exact == 0 (default): the gauge transformation of a sweep is the first-
+ * order step 1 + (alpha/2) L Delta made unitary by Gram-Schmidt.  exact != 0:
+ * g = exp((alpha/2) L Delta), evaluated exactly (Cayley-Hamilton form of the
+ * exponential series).  Both are readings of the steepest-descent step of the
+ * method (the paragraph after the display equation); they share the fixed
+ * points and differ at second order in alpha along the way.  Applies to
+ * lgf_fix and lgf_iterate, in both precisions. */
+int lgf_set_exponential(lgf_ctx *ctx, int exact);
+
 /* Exactly n_iter Fourier-accelerated updates of the links U (in place), with
  * no stopping test (n_iter >= 0).  res (may be NULL) gets F and theta of the
  * returned links.  LGF_FP64 only semantics: a LGF_MIXED context runs the

@@ -41,6 +41,7 @@ struct lgf_ctx {
     double p2max = 0;
     double theta_switch = 1e-8;
     bool accelerate = true;  // false: plain steepest descent (no transform)
+    bool exact_exp = false;  // true: g = exp((alpha/2) L Delta) exactly
 
     // working links, SoA-12: FP64 double buffer; the FP32 pair aliases L64[1]
     double2 *L64[2] = {nullptr, nullptr};
@@ -176,8 +177,8 @@ hipError_t enqueue_sweep(lgf_ctx *c, int cur, T half_alpha, bool accG, const fin
             return e;
     }
     return launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
-                            accG ? c->G32 : nullptr, half_alpha, c->partials, c->status, fp,
-                            c->stream);
+                            accG ? c->G32 : nullptr, half_alpha, c->exact_exp, c->partials,
+                            c->status, fp, c->stream);
 }
 
 int read_status(lgf_ctx *c, dev_status &out) {
@@ -309,8 +310,8 @@ int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
         chk(launch_fft_xy<T>(c->g, D, +1, P::tw(c), c->status, c->stream));
         chk(hipEventRecord(e[3], c->stream));
         chk(launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
-                             accG ? c->G32 : nullptr, half_alpha, c->partials, c->status,
-                             finp(c, false), c->stream));
+                             accG ? c->G32 : nullptr, half_alpha, c->exact_exp, c->partials,
+                             c->status, finp(c, false), c->stream));
         chk(hipEventRecord(e[4], c->stream));
         chk(launch_finalize(c->partials, c->nparts, c->status, finp(c, true, 0.0, n + 1, 1),
                             c->stream));
@@ -448,6 +449,12 @@ void lgf_destroy(lgf_ctx *c) {
 int lgf_set_acceleration(lgf_ctx *c, int on) {
     if (!c) return LGF_ERR_ARG;
     c->accelerate = on != 0;
+    return LGF_OK;
+}
+
+int lgf_set_exponential(lgf_ctx *c, int exact) {
+    if (!c) return LGF_ERR_ARG;
+    c->exact_exp = exact != 0;
     return LGF_OK;
 }
 

@@ -63,7 +63,7 @@ hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *part
 
 template <class T>
 hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void *LD, void *Dout,
-                         void *G, T c, double *partials, dev_status *status,
+                         void *G, T c, bool exact, double *partials, dev_status *status,
                          const fin_params &fp, hipStream_t st);
 
 // mode: -1 forward only, +1 inverse only (x,y pass: direction)

@@ -59,6 +59,15 @@ template <class T> LGF_HD void st(vec2_t<T> *p, cpx<T> a) {
     *p = v;
 }
 
+// Streaming store: written once and not read again by this kernel, so it is
+// marked non-temporal and does not displace lines that neighbouring blocks
+// are still going to read.
+template <class T> LGF_HD void st_stream(vec2_t<T> *p, cpx<T> a) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 v = {a.re, a.im};
+    __builtin_nontemporal_store(v, reinterpret_cast<v2 *>(p));
+}
+
 // 3x3 complex matrix, row-major.
 template <class T> struct mat3 {
     cpx<T> e[3][3];
@@ -152,7 +161,7 @@ template <class T>
 LGF_HD void store_link(vec2_t<T> *__restrict__ L, long S, int mu, long s, const mat3<T> &m) {
     vec2_t<T> *p = L + (long)mu * 6 * S + s;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) st<T>(p + (long)k * S, m.e[k / 3][k % 3]);
+    for (int k = 0; k < 6; ++k) st_stream<T>(p + (long)k * S, m.e[k / 3][k % 3]);
 }
 
 // g = reunit(1 + c * M) for the anti-hermitian traceless M whose 4 Fourier-
@@ -168,6 +177,95 @@ LGF_HD mat3<T> gauge_from_entries(cpx<T> f0, cpx<T> f1, cpx<T> f2, cpx<T> f3, T 
     g.e[1][2] = c * f2;
     reunitarise(g);
     return g;
+}
+
+// g = exp(c * M) exactly, for the same M.  With Q = -i c M (hermitian,
+// traceless) the Cayley-Hamilton theorem gives Q^3 = c1 Q + c0 with
+// c1 = Tr(Q^2)/2 and c0 = det Q, so every power of Q, and hence exp(iQ), is a
+// combination f0 + f1 Q + f2 Q^2.  The f_j are summed from the exponential
+// series with the powers reduced by that recurrence (Q^k = a + b Q + d Q^2,
+// Q^(k+1) = c0 d + (a + c1 d) Q + b Q^2), after scaling Q by 2^-s so that its
+// Frobenius norm is at most 1/2 (16 terms then leave an error below 1e-18);
+// s squarings in the same three-term algebra undo the scaling.  No matrix
+// products until the end, no transcendental functions.
+template <class T>
+LGF_HD mat3<T> gauge_exp_from_entries(cpx<T> f0, cpx<T> f1, cpx<T> f2, cpx<T> f3, T c) {
+    // Q = -i c M: diagonal c (a, b, -(a+b)); Q01 = -i c f0, Q02 = -i c f1, Q12 = -i c f2
+    const T q0 = c * f3.re, q1 = c * f3.im, q2 = -(q0 + q1);
+    const cpx<T> Q01 = mk<T>(c * f0.im, -c * f0.re), Q02 = mk<T>(c * f1.im, -c * f1.re),
+                 Q12 = mk<T>(c * f2.im, -c * f2.re);
+    const T n01 = norm2(Q01), n02 = norm2(Q02), n12 = norm2(Q12);
+    const T c1 = T(0.5) * (q0 * q0 + q1 * q1 + q2 * q2) + n01 + n02 + n12;
+    // det Q = q0 q1 q2 + 2 Re(Q01 Q12 Q20) - q0 |Q12|^2 - q1 |Q02|^2 - q2 |Q01|^2
+    const cpx<T> t = cmulc(cmul(Q01, Q12), Q02);
+    const T c0 = q0 * q1 * q2 + T(2) * t.re - q0 * n12 - q1 * n02 - q2 * n01;
+    // scaling: |Q|_F^2 = 2 c1 <= 1/4 (bounded loop: a non-finite c1 leaves it)
+    int sq = 0;
+    T r2 = T(2) * c1;
+    while (sq < 64 && r2 > T(0.25)) {
+        r2 *= T(0.25);
+        ++sq;
+    }
+    T sc = T(1);
+    for (int i = 0; i < sq; ++i) sc *= T(0.5);
+    T c1s = c1 * sc * sc, c0s = c0 * sc * sc * sc;
+    // series: sum_k i^k/k! (a_k, b_k, d_k)
+    cpx<T> F0 = mk<T>(0, 0), F1 = mk<T>(0, 0), F2 = mk<T>(0, 0), fac = mk<T>(1, 0);
+    T a = 1, b = 0, d = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        F0 = F0 + a * fac;
+        F1 = F1 + b * fac;
+        F2 = F2 + d * fac;
+        const T an = c0s * d, bn = fma(c1s, d, a);
+        d = b;
+        a = an;
+        b = bn;
+        fac = (T(1) / T(k + 1)) * mk<T>(-fac.im, fac.re);  // times i/(k+1)
+    }
+    // squaring: (F0 + F1 P + F2 P^2)^2 reduced with P^3 = c1s P + c0s, then P -> 2P
+    for (int i = 0; i < sq; ++i) {
+        const cpx<T> f12 = cmul(F1, F2), f22 = cmul(F2, F2);
+        const cpx<T> g0 = cmac(c0s * (T(2) * f12), F0, F0);
+        const cpx<T> g1 = cmac(c1s * (T(2) * f12) + c0s * f22, T(2) * F0, F1);
+        const cpx<T> g2 = cmac(cmac(c1s * f22, F1, F1), T(2) * F0, F2);
+        F0 = g0;
+        F1 = T(0.5) * g1;
+        F2 = T(0.25) * g2;
+        c1s *= T(4);
+        c0s *= T(8);
+    }
+    // rows 0, 1 of f0 + f1 Q + f2 Q^2
+    cpx<T> Q[3][3];
+    Q[0][0] = mk<T>(q0, 0);
+    Q[1][1] = mk<T>(q1, 0);
+    Q[2][2] = mk<T>(q2, 0);
+    Q[0][1] = Q01;
+    Q[0][2] = Q02;
+    Q[1][2] = Q12;
+    Q[1][0] = conjg(Q01);
+    Q[2][0] = conjg(Q02);
+    Q[2][1] = conjg(Q12);
+    mat3<T> g;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cpx<T> q2ij = cmul(Q[i][0], Q[0][j]);
+            q2ij = cmac(q2ij, Q[i][1], Q[1][j]);
+            q2ij = cmac(q2ij, Q[i][2], Q[2][j]);
+            cpx<T> e = cmac(cmul(F1, Q[i][j]), F2, q2ij);
+            if (i == j) e = e + F0;
+            g.e[i][j] = e;
+        }
+    rebuild_row2(g);
+    return g;
+}
+
+template <class T, bool EXACT>
+LGF_HD mat3<T> gauge_step(cpx<T> f0, cpx<T> f1, cpx<T> f2, cpx<T> f3, T c) {
+    if constexpr (EXACT) return gauge_exp_from_entries<T>(f0, f1, f2, f3, c);
+    else return gauge_from_entries<T>(f0, f1, f2, f3, c);
 }
 
 // The same from a Fourier field at site s.

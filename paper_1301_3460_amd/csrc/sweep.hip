@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 // fused update + next divergence
 // ---------------------------------------------------------------------------
 
-template <class T, bool ACC_G>
+template <class T, bool ACC_G, bool EXACT>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_update(geom g, const vec2_t<T> *__restrict__ Lin, vec2_t<T> *__restrict__ Lout,
              const vec2_t<T> *__restrict__ LD, vec2_t<T> *__restrict__ Dout,
@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 #pragma unroll
         for (int f = 0; f < 4; ++f) own[f] = ld<T>(LD + (long)f * g.S + s);
         fetch(0, d[0]);
-        const mat3<T> g0 = gauge_from_entries<T>(own[0], own[1], own[2], own[3], c);
+        const mat3<T> g0 = gauge_step<T, EXACT>(own[0], own[1], own[2], own[3], c);
         xacc<T> X;
         xacc_zero(X);
         T tr = 0;
@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
             if (h < 7) fetch(h + 1, d[(h + 1) & 1]);
             __builtin_amdgcn_sched_barrier(0);
             const half &cur = d[h & 1];
-            const mat3<T> gn = gauge_from_entries<T>(cur.f[0], cur.f[1], cur.f[2], cur.f[3], c);
+            const mat3<T> gn = gauge_step<T, EXACT>(cur.f[0], cur.f[1], cur.f[2], cur.f[3], c);
             mat3<T> u;
 #pragma unroll
             for (int k = 0; k < 6; ++k) u.e[k / 3][k % 3] = cur.u[k];
@@ -243,10 +243,10 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         cpx<T> f0, f1, f2, f3;
         ts = (double)delta_pack(X, f0, f1, f2, f3);
         fs = (double)tr;
-        st<T>(Dout + s, f0);
-        st<T>(Dout + g.S + s, f1);
-        st<T>(Dout + 2 * g.S + s, f2);
-        st<T>(Dout + 3 * g.S + s, f3);
+        st_stream<T>(Dout + s, f0);
+        st_stream<T>(Dout + g.S + s, f1);
+        st_stream<T>(Dout + 2 * g.S + s, f2);
+        st_stream<T>(Dout + 3 * g.S + s, f3);
         if constexpr (ACC_G) {
             // G(x) <- g(x) G(x), rows 0,1 kept (12 reals)
             mat3<T> G0;
@@ -703,27 +703,31 @@ template hipError_t launch_div_reduce<float>(const geom &, const void *, void *,
 
 template <class T>
 hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void *LD, void *Dout,
-                         void *G, T c, double *partials, dev_status *status, const fin_params &fp,
-                         hipStream_t st) {
-    if (G)
-        k_update<T, true><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
+                         void *G, T c, bool exact, double *partials, dev_status *status,
+                         const fin_params &fp, hipStream_t st) {
+    auto go = [&](auto kernel, vec2_t<T> *Gp) {
+        kernel<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
             g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout),
-            static_cast<const vec2_t<T> *>(LD), static_cast<vec2_t<T> *>(Dout),
-            static_cast<vec2_t<T> *>(G), c, partials, status);
-    else
-        k_update<T, false><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
-            g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout),
-            static_cast<const vec2_t<T> *>(LD), static_cast<vec2_t<T> *>(Dout), nullptr, c,
-            partials, status);
+            static_cast<const vec2_t<T> *>(LD), static_cast<vec2_t<T> *>(Dout), Gp, c, partials,
+            status);
+    };
+    auto Gp = static_cast<vec2_t<T> *>(G);
+    if (G) {
+        if (exact) go(k_update<T, true, true>, Gp);
+        else go(k_update<T, true, false>, Gp);
+    } else {
+        if (exact) go(k_update<T, false, true>, nullptr);
+        else go(k_update<T, false, false>, nullptr);
+    }
     if (fp.enabled) k_finalize<<<1, FIN_BLOCK, 0, st>>>(partials, site_blocks(g.V), status, fp);
     return hipGetLastError();
 }
 template hipError_t launch_update<double>(const geom &, const void *, void *, const void *, void *,
-                                          void *, double, double *, dev_status *,
+                                          void *, double, bool, double *, dev_status *,
                                           const fin_params &, hipStream_t);
 template hipError_t launch_update<float>(const geom &, const void *, void *, const void *, void *,
-                                         void *, float, double *, dev_status *, const fin_params &,
-                                         hipStream_t);
+                                         void *, float, bool, double *, dev_status *,
+                                         const fin_params &, hipStream_t);
 
 hipError_t launch_reorder_fields(const geom &g, const double2 *in, long si, double2 *out, long so,
                                  int to_natural, hipStream_t st) {

@@ -25,19 +25,23 @@ WORKLOADS = {
     "32^4": {"L": (32, 32, 32, 32), "eps": [0.6, 0.45, 0.35], "alpha": 0.08, "tol": 1e-15},
     "8^4": {"L": (8, 8, 8, 8), "eps": [0.5], "alpha": 0.08, "tol": 1e-12},
     "48^3x96": {"L": (48, 48, 48, 96), "eps": [0.45], "alpha": 0.08, "tol": 1e-15},
+    # the same 32^4 input, solved with the exactly exponentiated step
+    "32^4-exp": {"L": (32, 32, 32, 32), "eps": [0.45], "alpha": 0.08, "tol": 1e-15,
+                 "seeds": "32^4", "exact_exp": True},
 }
 
 
 def main(name: str) -> None:
     w = WORKLOADS[name]
+    exact = w.get("exact_exp", False)
     out = {"workload": name, "L": w["L"], "alpha": w["alpha"], "tol": w["tol"],
-           "threads": oracle.get_threads(), "runs": []}
+           "exact_exp": exact, "threads": oracle.get_threads(), "runs": []}
     for eps in w["eps"]:
-        seed = inputs.CONFIG_SEEDS[(name, eps)]
+        seed = inputs.CONFIG_SEEDS[(w.get("seeds", name), eps)]
         U, _ = inputs.make_config(w["L"], eps, seed)
         P0 = oracle.plaquette(U)
         t0 = time.time()
-        r = oracle.fix(U, w["alpha"], w["tol"], 2000)
+        r = oracle.fix(U, w["alpha"], w["tol"], 2000, exact_exp=exact)
         dt = time.time() - t0
         mu, md = oracle.unitarity(r["U"])
         run = {"eps": eps, "seed": seed, "status": r["status"], "iterations": r["iterations"],
@@ -50,7 +54,7 @@ def main(name: str) -> None:
         out["runs"].append(run)
         del U, r
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                        f"oracle_{name.replace('^', '')}.json")
+                        f"oracle_{name.replace('^', '').replace('-', '')}.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path)

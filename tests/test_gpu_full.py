@@ -80,6 +80,41 @@ def test_lockstep_sweep_32x4(lgf_gpu, configs):
     assert r.F == pytest.approx(_golden()[0.45]["F_hist"][1], abs=1e-14)
 
 
+GOLDEN_EXP = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                          "oracle_324exp.json")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_32x4_exact_exp(lgf_gpu, configs, precision):
+    """The exactly exponentiated step at 32^4 (oracle run with the same flag)."""
+    with open(GOLDEN_EXP) as f:
+        ref = json.load(f)["runs"][0]
+    U = _config(configs, ref["eps"])
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, 0.08, 1e-15, precision=precision, max_iter=2000, exact_exp=True)
+    assert r.status == 0
+    out = Ug.cpu().numpy()
+    del Ug
+    assert oracle.theta(out) < 1e-15
+    assert abs(r.F - ref["F"]) <= 1e-12
+    assert abs(oracle.plaquette(out) - ref["plaquette_in"]) <= 1e-12
+    mu, md = oracle.unitarity(out)
+    assert mu <= 1e-13 and md <= 1e-13
+    if precision == "fp64":
+        assert abs(r.iterations - ref["iterations"]) <= 1
+
+
+def test_lockstep_sweep_32x4_exact_exp(lgf_gpu, configs):
+    with open(GOLDEN_EXP) as f:
+        ref = json.load(f)["runs"][0]
+    U = _config(configs, ref["eps"])
+    Ug = gpu(U)
+    r = lgf_gpu.iterate(Ug, 0.08, 2, exact_exp=True)
+    del Ug
+    assert r.theta == pytest.approx(ref["theta_hist"][2], rel=1e-11)
+    assert r.F == pytest.approx(ref["F_hist"][2], abs=1e-14)
+
+
 GOLDEN48 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
                         "oracle_483x96.json")
 L48 = (48, 48, 48, 96)

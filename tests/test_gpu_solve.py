@@ -155,3 +155,34 @@ def test_plain_steepest_descent_solve(lgf_gpu):
     assert oracle.theta(cpu(Ug)) < 1e-10
     fa = lgf_gpu.fix(gpu(U), ALPHA, 1e-10, max_iter=3000)
     assert r.iterations > 2 * fa.iterations
+
+
+# ------------------------------------------------------------ exact exponential
+
+@pytest.mark.parametrize("L,accelerate", [((4, 4, 4, 4), True), ((4, 6, 8, 12), True),
+                                          ((8, 8, 6, 4), False)])
+def test_exact_exp_lockstep(lgf_gpu, L, accelerate):
+    U, _ = inputs.make_config(L, 0.5, 70 + sum(L))
+    for step in range(3):
+        Ug = gpu(U)
+        lgf_gpu.iterate(Ug, ALPHA, 1, accelerate=accelerate, exact_exp=True)
+        got = cpu(Ug)
+        ref = oracle.fix(U, ALPHA, 0.0, 1, accelerate=accelerate, exact_exp=True)["U"]
+        assert np.max(np.abs(got - ref)) < 1e-13, step
+        U = got
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_exact_exp_solve_matches_oracle(lgf_gpu, precision):
+    U, _ = inputs.make_config((8, 8, 8, 8), 0.5, inputs.CONFIG_SEEDS[("8^4", 0.5)])
+    ref = oracle.fix(U, ALPHA, 1e-14, 1000, exact_exp=True)
+    assert ref["status"] == 0
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, ALPHA, 1e-14, precision=precision, max_iter=1000, exact_exp=True)
+    assert r.status == 0
+    _check_solution(cpu(Ug), U, 1e-14, r.F)
+    assert abs(r.F - ref["F"]) < 1e-12
+    if precision == "fp64":
+        assert abs(r.iterations - ref["iterations"]) <= 1
+    first_order = oracle.fix(U, ALPHA, 1e-14, 1000)
+    assert abs(r.F - first_order["F"]) < 1e-12

@@ -26,6 +26,7 @@ TOL = 1e-15
 L = (32, 32, 32, 32)
 EPS_ALL = (0.6, 0.45, 0.35)
 EPS_MAIN = 0.45
+BYTES_UPDATE_18 = 4 * 144 * 2 + 128  # update with 18-real links: R+W 4 x 144 B, R+W 64 B
 SD_TOL = 1e-10  # plain steepest descent needs thousands of sweeps at 32^4
 # algorithmic bytes per site of each sweep kernel (FP64 / FP32 with G)
 BYTES_PER_SITE = {
@@ -208,6 +209,33 @@ def main() -> int:
         ctx.set_exponential(False)
         variants[f"exact_exp/{prec}"] = entry
         log(f"exact exponential {prec}: {entry}")
+    # 18-real working links (all three rows stored) against the 12-real default
+    ctx64.set_link_format(18)
+    work.copy_(U0)
+    ctx64.iterate(work, ALPHA, args.warmup)
+    work.copy_(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx64.iterate(work, ALPHA, args.steps)
+    torch.cuda.synchronize()
+    ips18 = args.steps / (time.perf_counter() - t0)
+    upd18 = ctx64.profile(U0, ALPHA, 20)["update"]
+    times = []
+    for _ in range(args.solves):
+        work.copy_(U0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx64.fix(work, ALPHA, TOL, 2000)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ctx64.set_link_format(12)
+    variants["link18/fp64"] = {
+        "sweeps_per_s": round(ips18, 1), "update_ms": round(upd18, 5),
+        "update_GBps": round(BYTES_UPDATE_18 * V / (upd18 * 1e-3) / 1e9, 1),
+        "update_bytes_per_site": BYTES_UPDATE_18,
+        "solve_ms": round(1e3 * float(np.median(times)), 3), "iterations": res.iterations,
+        "F": res.F, "dF_vs_oracle": abs(res.F - golden[EPS_MAIN]["F"]) if golden else None}
+    log(f"18-real links: {variants['link18/fp64']}")
     ctx64.set_acceleration(False)
     work.copy_(U0)
     torch.cuda.synchronize()

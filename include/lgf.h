@@ -107,6 +107,17 @@ int lgf_set_acceleration(lgf_ctx *ctx, int on);
  * lgf_fix and lgf_iterate, in both precisions. */
 int lgf_set_exponential(lgf_ctx *ctx, int exact);
 
+/* Storage of the working links during lgf_fix / lgf_iterate: nreal = 12
+ * (default; the paper's "12 real number representation": rows 0 and 1, row 2
+ * rebuilt as conj(row0 x row1) on every load) or 18 (all three rows stored, no
+ * rebuild, 50% more link traffic).  The caller's links are always full 3x3
+ * complex128; the other entry points always use 12.  Changing the format
+ * reallocates the context's link buffers (synchronises the stream).
+ * LGF_ERR_ARG for another nreal; LGF_ERR_OOM if the new buffers do not fit (the
+ * context then holds 12-real buffers again, or none, which later calls
+ * report). */
+int lgf_set_link_format(lgf_ctx *ctx, int nreal);
+
 /* Exactly n_iter Fourier-accelerated updates of the links U (in place), with
  * no stopping test (n_iter >= 0).  res (may be NULL) gets F and theta of the
  * returned links.  LGF_FP64 only semantics: a LGF_MIXED context runs the

@@ -87,6 +87,7 @@ def load(path: str | None = None):
         "lgf_set_theta_switch": (c.c_int, [vp, c.c_double]),
         "lgf_set_acceleration": (c.c_int, [vp, c.c_int]),
         "lgf_set_exponential": (c.c_int, [vp, c.c_int]),
+        "lgf_set_link_format": (c.c_int, [vp, c.c_int]),
         "lgf_iterate": (c.c_int, [vp, vp, c.c_double, c.c_int, c.POINTER(_Result)]),
         "lgf_fix": (c.c_int, [vp, vp, c.c_double, c.c_double, c.c_int, c.POINTER(_Result)]),
         "lgf_functional": (c.c_int, [vp, vp, vp, dp]),
@@ -186,6 +187,13 @@ class Context:
         """True: g = exp((alpha/2) L Delta) exactly; False (default): first-order
         step made unitary by Gram-Schmidt."""
         rc = self._lib.lgf_set_exponential(self._h, 1 if exact else 0)
+        if rc:
+            self._err(rc)
+
+    def set_link_format(self, nreal: int):
+        """12 (default, rows 0,1 stored) or 18 (all rows stored) reals per
+        working link in fix/iterate."""
+        rc = self._lib.lgf_set_link_format(self._h, int(nreal))
         if rc:
             self._err(rc)
 
@@ -346,22 +354,26 @@ def _ctx(U, precision="fp64") -> Context:
 
 
 def fix(U, alpha=0.08, theta_tol=1e-15, precision="fp64", max_iter=10000, theta_switch=1e-8,
-        accelerate=True, exact_exp=False):
+        accelerate=True, exact_exp=False, link_format=12):
     """Gauge-fix U in place; returns a Result (iterations, F, theta, status).
     accelerate=False runs plain (unaccelerated) steepest descent; exact_exp=True
-    exponentiates the step exactly."""
+    exponentiates the step exactly; link_format=18 stores all three rows of
+    the working links."""
     c = _ctx(U, precision)
     if precision == "mixed":
         c.set_theta_switch(theta_switch)
     c.set_acceleration(accelerate)
     c.set_exponential(exact_exp)
+    c.set_link_format(link_format)
     return c.fix(U, alpha, theta_tol, max_iter)
 
 
-def iterate(U, alpha=0.08, n=1, precision="fp64", accelerate=True, exact_exp=False):
+def iterate(U, alpha=0.08, n=1, precision="fp64", accelerate=True, exact_exp=False,
+            link_format=12):
     c = _ctx(U, precision)
     c.set_acceleration(accelerate)
     c.set_exponential(exact_exp)
+    c.set_link_format(link_format)
     return c.iterate(U, alpha, n)
 
 

@@ -239,15 +239,41 @@ int status_to_code(int code) {
     }
 }
 
+// Geometry for the entry points that always work on 12-real links (they pack
+// the caller's links themselves).
+geom g12(const lgf_ctx *c) {
+    geom g = c->g;
+    g.nr = 2;
+    return g;
+}
+
+// (Re)allocate the working link buffers for the context's link format: each
+// holds 4 links x 3*nr complex entries per site (FP64); the FP32 pair aliases
+// the second buffer.
+bool alloc_links(lgf_ctx *c) {
+    for (auto &p : c->L64) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    }
+    const size_t n = (size_t)12 * c->g.nr * c->g.S;
+    for (auto &p : c->L64)
+        if (hipMalloc((void **)&p, n * sizeof(double2)) != hipSuccess) return false;
+    c->L32[0] = reinterpret_cast<float2 *>(c->L64[1]);
+    c->L32[1] = reinterpret_cast<float2 *>(c->L64[1]) + n;
+    return true;
+}
+
 int check_ctx(lgf_ctx *c) {
     if (!c) return LGF_ERR_ARG;
+    if (!c->L64[0] || !c->L64[1])
+        return fail(c, LGF_ERR_OOM, "link buffers lost in a failed format change");
     HIPCHK(c, hipSetDevice(c->device));
     return LGF_OK;
 }
 
 // Pack caller links into FP64 working buffer 0, then F/theta of them.
 int eval_links64(lgf_ctx *c, const double *U, double &F, double &theta) {
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->g.nr, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<double>(c->g, c->L64[0], c->D64[0], c->partials, c->status,
                                         finp(c, false), c->stream));
@@ -286,7 +312,7 @@ template <class T>
 int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
     using P = prec<T>;
     const bool accG = std::is_same<T, float>::value;
-    HIPCHK(c, launch_pack_links<T>(U, P::links(c, 0), c->g.V, c->g.S, c->stream));
+    HIPCHK(c, launch_pack_links<T>(U, P::links(c, 0), c->g.V, c->g.S, c->g.nr, c->stream));
     if (accG) HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->g.S, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<T>(c->g, P::links(c, 0), P::field(c, 0), c->partials, c->status,
@@ -380,8 +406,7 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
     auto alloc = [&](void **p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; };
     bool ok = true;
     const long S = c->g.S;
-    ok = ok && alloc((void **)&c->L64[0], (size_t)24 * S * sizeof(double2));
-    ok = ok && alloc((void **)&c->L64[1], (size_t)24 * S * sizeof(double2));
+    ok = ok && alloc_links(c);
     ok = ok && alloc((void **)&c->D64[0], (size_t)4 * S * sizeof(double2));
     ok = ok && alloc((void **)&c->D64[1], (size_t)4 * S * sizeof(double2));
     if (precision == LGF_MIXED) ok = ok && alloc((void **)&c->G32, (size_t)6 * S * sizeof(float2));
@@ -401,9 +426,6 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
         lgf_destroy(c);
         return fail(nullptr, LGF_ERR_OOM, "out of device memory");
     }
-    // FP32 working links live in the second FP64 buffer (2 x 12 floats per link)
-    c->L32[0] = reinterpret_cast<float2 *>(c->L64[1]);
-    c->L32[1] = reinterpret_cast<float2 *>(c->L64[1]) + (size_t)24 * S;
 
     auto tw64 = make_twiddles<double2>();
     auto tw32 = make_twiddles<float2>();
@@ -452,6 +474,22 @@ int lgf_set_acceleration(lgf_ctx *c, int on) {
     return LGF_OK;
 }
 
+int lgf_set_link_format(lgf_ctx *c, int nreal) {
+    if (!c) return LGF_ERR_ARG;
+    if (nreal != 12 && nreal != 18) return fail(c, LGF_ERR_ARG, "link format must be 12 or 18");
+    const int nr = nreal / 6;
+    if (nr == c->g.nr) return LGF_OK;
+    if (hipSetDevice(c->device) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+        return fail(c, LGF_ERR_DEVICE, "device unavailable");
+    c->g.nr = nr;
+    if (!alloc_links(c)) {
+        c->g.nr = 2;
+        (void)alloc_links(c);  // on failure the buffers stay null; check_ctx reports it
+        return fail(c, LGF_ERR_OOM, "out of device memory (links)");
+    }
+    return LGF_OK;
+}
+
 int lgf_set_exponential(lgf_ctx *c, int exact) {
     if (!c) return LGF_ERR_ARG;
     c->exact_exp = exact != 0;
@@ -473,7 +511,7 @@ static int solve(lgf_ctx *c, double *U, double alpha, double tol, int max_iter, 
     int cur64 = 0;
     if (c->precision == LGF_MIXED) {
         // FP32 phase on a downcast copy; G accumulates the applied transformation
-        HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g.V, c->g.S, c->stream));
+        HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g.V, c->g.S, c->g.nr, c->stream));
         HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->g.S, c->stream));
         const double tol32 = std::max(tol, c->theta_switch);
         rc = run_phase<float>(c, alpha, tol32, max_iter, true, 0, st);
@@ -490,14 +528,14 @@ static int solve(lgf_ctx *c, double *U, double alpha, double tol, int max_iter, 
             cur64 = n64 & 1;
         }
     } else {
-        HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
+        HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->g.nr, c->stream));
         rc = run_phase<double>(c, alpha, tol, max_iter, false, 0, st);
         if (rc) return rc;
         n64 = st.n;
         code = st.code;
         cur64 = n64 & 1;
     }
-    HIPCHK(c, launch_unpack_links(c->L64[cur64], U, c->g.V, c->g.S, c->stream));
+    HIPCHK(c, launch_unpack_links(c->L64[cur64], U, c->g.V, c->g.S, c->g.nr, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->hist_len = n32 + n64 + 1;
     const int out = status_to_code(code);
@@ -536,20 +574,20 @@ int lgf_iterate(lgf_ctx *c, double *U, double alpha, int n_iter, lgf_result *res
     dev_status st{};
     int n32 = 0, n64 = 0, cur64 = 0;
     if (c->precision == LGF_MIXED) {
-        HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g.V, c->g.S, c->stream));
+        HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g.V, c->g.S, c->g.nr, c->stream));
         HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->g.S, c->stream));
         rc = run_phase<float>(c, alpha, 0.0, n_iter, true, 0, st);
         if (rc) return rc;
         n32 = st.n;
         HIPCHK(c, launch_switch(c->g, c->G32, U, c->L64[0], c->stream));
     } else {
-        HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
+        HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->g.nr, c->stream));
         rc = run_phase<double>(c, alpha, 0.0, n_iter, false, 0, st);
         if (rc) return rc;
         n64 = st.n;
         cur64 = n64 & 1;
     }
-    HIPCHK(c, launch_unpack_links(c->L64[cur64], U, c->g.V, c->g.S, c->stream));
+    HIPCHK(c, launch_unpack_links(c->L64[cur64], U, c->g.V, c->g.S, c->g.nr, c->stream));
     double F = st.F, th = st.theta;
     if (c->precision == LGF_MIXED) {
         rc = eval_links64(c, U, F, th);
@@ -578,7 +616,7 @@ int lgf_functional(lgf_ctx *c, const double *U, const double *g, double *F) {
         double th;
         return eval_links64(c, U, *F, th);
     }
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, 2, c->stream));
     HIPCHK(c, launch_functional_g(c->g, c->L64[0], g, c->partials, c->stream));
     double A, B;
     rc = sum_partials(c, A, B);
@@ -601,7 +639,7 @@ int lgf_plaquette(lgf_ctx *c, const double *U, double *P) {
     if (!U || !P) return fail(c, LGF_ERR_ARG, "null argument");
     int rc = check_ctx(c);
     if (rc) return rc;
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, 2, c->stream));
     HIPCHK(c, launch_plaquette(c->g, c->L64[0], c->partials, c->stream));
     double A, B;
     rc = sum_partials(c, A, B);
@@ -615,7 +653,7 @@ int lgf_divergence(lgf_ctx *c, const double *U, double *Delta) {
     if (!U || !Delta) return fail(c, LGF_ERR_ARG, "null argument");
     int rc = check_ctx(c);
     if (rc) return rc;
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->g.nr, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<double>(c->g, c->L64[0], c->D64[0], c->partials, c->status,
                                         finp(c, false), c->stream));
@@ -688,10 +726,10 @@ int lgf_functional_omega_grad(lgf_ctx *c, const double *U, const double *omega, 
     if (rc) return rc;
     if ((rc = ensure_diff_scratch(c))) return rc;
     HIPCHK(c, launch_expm_sites(omega, c->gaos, c->g.V, c->stream));
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, 2, c->stream));
     HIPCHK(c, launch_rotate_links(c->g, c->L64[0], c->gaos, c->Lrot, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
-    HIPCHK(c, launch_div_reduce<double>(c->g, c->Lrot, c->D64[0], c->partials, c->status,
+    HIPCHK(c, launch_div_reduce<double>(g12(c), c->Lrot, c->D64[0], c->partials, c->status,
                                         finp(c, false), c->stream));
     double A, B;
     rc = sum_partials(c, A, B);
@@ -708,7 +746,7 @@ int lgf_theta_grad(lgf_ctx *c, const double *U, const double *eps, double *theta
     int rc = check_ctx(c);
     if (rc) return rc;
     if ((rc = ensure_diff_scratch(c))) return rc;
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, 2, c->stream));
     const void *Lw = c->L64[0];
     if (eps) {
         HIPCHK(c, launch_expm_sites(eps, c->gaos, 4 * c->g.V, c->stream));
@@ -716,7 +754,7 @@ int lgf_theta_grad(lgf_ctx *c, const double *U, const double *eps, double *theta
         Lw = c->Lrot;
     }
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
-    HIPCHK(c, launch_div_reduce<double>(c->g, Lw, c->D64[0], c->partials, c->status,
+    HIPCHK(c, launch_div_reduce<double>(g12(c), Lw, c->D64[0], c->partials, c->status,
                                         finp(c, false), c->stream));
     double A, B;
     rc = sum_partials(c, A, B);

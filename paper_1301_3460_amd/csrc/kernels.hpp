@@ -47,6 +47,8 @@ struct geom {
     // site-kernel tiling (see block_site): 0 consecutive sites; 1 64 xy-sites
     // x 4 t (needs Lx*Ly % 64 == 0, Lt % 4 == 0), in groups of sgroup segments
     int tblock = 0, sgroup = 1;
+    // stored rows per working link: 2 (12-real, row 2 rebuilt) or 3 (18-real)
+    int nr = 2;
 };
 
 constexpr int SITE_BLOCK = 256;  // threads per block of the site kernels
@@ -54,8 +56,9 @@ inline int site_blocks(long V) { return (int)((V + SITE_BLOCK - 1) / SITE_BLOCK)
 
 // All launchers enqueue on `st` and return hipGetLastError().
 template <class T>
-hipError_t launch_pack_links(const double *Uaos, void *L, long V, long S, hipStream_t st);
-hipError_t launch_unpack_links(const void *L64, double *Uaos, long V, long S, hipStream_t st);
+hipError_t launch_pack_links(const double *Uaos, void *L, long V, long S, int nr, hipStream_t st);
+hipError_t launch_unpack_links(const void *L64, double *Uaos, long V, long S, int nr,
+                               hipStream_t st);
 
 template <class T>
 hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *partials,

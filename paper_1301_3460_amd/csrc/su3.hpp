@@ -114,12 +114,13 @@ template <class T> LGF_HD void reunitarise(mat3<T> &m) {
     rebuild_row2(m);
 }
 
-// Rows 0,1 of A * B * C^dagger, then row 2 rebuilt (the result is SU(3)
-// when A, B, C are).
-template <class T> LGF_HD mat3<T> mul_abcd(const mat3<T> &A, const mat3<T> &B, const mat3<T> &C) {
+// A * B * C^dagger.  ROWS = 2: rows 0,1 by products, row 2 rebuilt (the
+// result is SU(3) when A, B, C are); ROWS = 3: all three rows by products.
+template <int ROWS = 2, class T>
+LGF_HD mat3<T> mul_abcd(const mat3<T> &A, const mat3<T> &B, const mat3<T> &C) {
     mat3<T> r;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < ROWS; ++i) {
         cpx<T> ab[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -134,34 +135,36 @@ template <class T> LGF_HD mat3<T> mul_abcd(const mat3<T> &A, const mat3<T> &B, c
             r.e[i][j] = cmacc(acc, ab[2], C.e[j][2]);
         }
     }
-    rebuild_row2(r);
+    if constexpr (ROWS == 2) rebuild_row2(r);
     return r;
 }
 
 // ------------------------------------------------------------------------
 // Storage layouts
-//   links SoA-12:  L[(mu*6 + k)*S + s], k = 3*row + col, row in {0,1}
+//   links SoA:     L[(mu*3*NR + k)*S + s], k = 3*row + col for the NR stored
+//                  rows: NR = 2 is the 12-real form (rows 0,1; row 2 rebuilt
+//                  as conj(row0 x row1)), NR = 3 the 18-real form (no rebuild)
 //   Fourier field: D[f*S + s], f = 0..3 holding the independent entries of
 //                  an anti-hermitian traceless matrix:
 //                  f0 = M01, f1 = M02, f2 = M12,
 //                  f3 = (Im M00) + i (Im M11)
 // ------------------------------------------------------------------------
 
-template <class T>
+template <class T, int NR = 2>
 LGF_HD mat3<T> load_link(const vec2_t<T> *__restrict__ L, long S, int mu, long s) {
     mat3<T> m;
-    const vec2_t<T> *p = L + (long)mu * 6 * S + s;
+    const vec2_t<T> *p = L + (long)mu * 3 * NR * S + s;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) m.e[k / 3][k % 3] = ld<T>(p + (long)k * S);
-    rebuild_row2(m);
+    for (int k = 0; k < 3 * NR; ++k) m.e[k / 3][k % 3] = ld<T>(p + (long)k * S);
+    if constexpr (NR == 2) rebuild_row2(m);
     return m;
 }
 
-template <class T>
+template <class T, int NR = 2>
 LGF_HD void store_link(vec2_t<T> *__restrict__ L, long S, int mu, long s, const mat3<T> &m) {
-    vec2_t<T> *p = L + (long)mu * 6 * S + s;
+    vec2_t<T> *p = L + (long)mu * 3 * NR * S + s;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) st_stream<T>(p + (long)k * S, m.e[k / 3][k % 3]);
+    for (int k = 0; k < 3 * NR; ++k) st_stream<T>(p + (long)k * S, m.e[k / 3][k % 3]);
 }
 
 // g = reunit(1 + c * M) for the anti-hermitian traceless M whose 4 Fourier-

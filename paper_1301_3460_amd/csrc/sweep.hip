@@ -12,6 +12,8 @@
 //   finalize    fixed-order sum of the partials, stopping test
 // Links are double-buffered (the update reads U_mu(x-mu) of other threads),
 // as are the Fourier fields.
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace lgf {
@@ -20,8 +22,8 @@ namespace lgf {
 // layout conversion
 // ---------------------------------------------------------------------------
 
-// complex128 [4][V][3][3] -> SoA-12 of type T (rows 0,1)
-template <class T>
+// complex128 [4][V][3][3] -> SoA of type T (the first NR rows)
+template <class T, int NR>
 __global__ void __launch_bounds__(256) k_pack_links(const double2 *__restrict__ U,
                                                     vec2_t<T> *__restrict__ L, long V, long S) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -30,22 +32,23 @@ __global__ void __launch_bounds__(256) k_pack_links(const double2 *__restrict__ 
     const long s = i - (long)mu * V;
     const double2 *u = U + i * 9;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < 3 * NR; ++k) {
         double2 v = u[k];
         vec2_t<T> w;
         w.x = (T)v.x;
         w.y = (T)v.y;
-        L[((long)mu * 6 + k) * S + s] = w;
+        L[((long)mu * 3 * NR + k) * S + s] = w;
     }
 }
 
+template <int NR>
 __global__ void __launch_bounds__(256) k_unpack_links(const double2 *__restrict__ L,
                                                       double2 *__restrict__ U, long V, long S) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 4 * V) return;
     const int mu = (int)(i / V);
     const long s = i - (long)mu * V;
-    mat3<double> m = load_link<double>(L, S, mu, s);
+    mat3<double> m = load_link<double, NR>(L, S, mu, s);
     double2 *u = U + i * 9;
 #pragma unroll
     for (int k = 0; k < 9; ++k) u[k] = make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
@@ -147,7 +150,7 @@ __device__ __forceinline__ void finalize_state(double A, double B, dev_status *s
 // divergence and reductions of given links (first sweep of a solve)
 // ---------------------------------------------------------------------------
 
-template <class T>
+template <class T, int NR>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_div_reduce(geom g, const vec2_t<T> *__restrict__ L, vec2_t<T> *__restrict__ D,
                  double *__restrict__ partials, const dev_status *__restrict__ status) {
@@ -161,10 +164,10 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         T tr = 0;
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
-            mat3<T> u = load_link<T>(L, g.S, mu, s);
+            mat3<T> u = load_link<T, NR>(L, g.S, mu, s);
             tr += retrace(u);
             xacc_add(X, u, T(-1));
-            mat3<T> um = load_link<T>(L, g.S, mu, n.m[mu]);
+            mat3<T> um = load_link<T, NR>(L, g.S, mu, n.m[mu]);
             xacc_add(X, um, T(1));
         }
         cpx<T> f0, f1, f2, f3;
@@ -182,7 +185,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 // fused update + next divergence
 // ---------------------------------------------------------------------------
 
-template <class T, bool ACC_G, bool EXACT>
+template <class T, bool ACC_G, bool EXACT, int NR>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_update(geom g, const vec2_t<T> *__restrict__ Lin, vec2_t<T> *__restrict__ Lout,
              const vec2_t<T> *__restrict__ LD, vec2_t<T> *__restrict__ Dout,
@@ -194,12 +197,12 @@ __global__ void __launch_bounds__(SITE_BLOCK)
     if (s < g.V) {
         const nbr n = neighbours(g, s);
         // Eight half-steps h = 2 mu + b: b = 0 transforms the link U_mu(x)
-        // with g(x+mu), b = 1 the link U_mu(x-mu) with g(x-mu).  Each needs 10
-        // loads (4 field entries, 6 link entries); the loads of half-step h+1
+        // with g(x+mu), b = 1 the link U_mu(x-mu) with g(x-mu).  Each needs
+        // 4 field entries and 3*NR link entries; the loads of half-step h+1
         // are issued before half-step h is computed (software pipelining),
         // so every wave keeps the next memory round trip in flight.
         struct half {
-            cpx<T> f[4], u[6];
+            cpx<T> f[4], u[3 * NR];
         };
         auto fetch = [&](int h, half &d) {
             const int mu = h >> 1;
@@ -207,9 +210,9 @@ __global__ void __launch_bounds__(SITE_BLOCK)
             const long sl = (h & 1) ? n.m[mu] : s;
 #pragma unroll
             for (int f = 0; f < 4; ++f) d.f[f] = ld<T>(LD + (long)f * g.S + sf);
-            const vec2_t<T> *lp = Lin + (long)mu * 6 * g.S + sl;
+            const vec2_t<T> *lp = Lin + (long)mu * 3 * NR * g.S + sl;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) d.u[k] = ld<T>(lp + (long)k * g.S);
+            for (int k = 0; k < 3 * NR; ++k) d.u[k] = ld<T>(lp + (long)k * g.S);
         };
         half d[2];
         cpx<T> own[4];
@@ -228,15 +231,15 @@ __global__ void __launch_bounds__(SITE_BLOCK)
             const mat3<T> gn = gauge_step<T, EXACT>(cur.f[0], cur.f[1], cur.f[2], cur.f[3], c);
             mat3<T> u;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) u.e[k / 3][k % 3] = cur.u[k];
-            rebuild_row2(u);
+            for (int k = 0; k < 3 * NR; ++k) u.e[k / 3][k % 3] = cur.u[k];
+            if constexpr (NR == 2) rebuild_row2(u);
             if ((h & 1) == 0) {
-                const mat3<T> un = mul_abcd(g0, u, gn);  // g(x) U_mu(x) g(x+mu)^+
-                store_link<T>(Lout, g.S, h >> 1, s, un);
+                const mat3<T> un = mul_abcd<NR>(g0, u, gn);  // g(x) U_mu(x) g(x+mu)^+
+                store_link<T, NR>(Lout, g.S, h >> 1, s, un);
                 tr += retrace(un);
                 xacc_add(X, un, T(-1));
             } else {
-                const mat3<T> umn = mul_abcd(gn, u, g0);  // g(x-mu) U_mu(x-mu) g(x)^+
+                const mat3<T> umn = mul_abcd<NR>(gn, u, g0);  // g(x-mu) U_mu(x-mu) g(x)^+
                 xacc_add(X, umn, T(1));
             }
         }
@@ -344,6 +347,7 @@ __device__ __forceinline__ mat3<double> load_G_fp64(const float2 *__restrict__ G
 }
 
 // U_mu(x) = G(x) U0_mu(x) G(x+mu)^dagger in FP64, G reunitarised in FP64
+template <int NR>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_switch(geom g, const float2 *__restrict__ G, const double2 *__restrict__ U0,
              double2 *__restrict__ L) {
@@ -357,9 +361,9 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         mat3<double> u;
         const double2 *p = U0 + ((long)mu * g.V + s) * 9;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) u.e[k / 3][k % 3] = mk<double>(p[k].x, p[k].y);
-        rebuild_row2(u);
-        store_link<double>(L, g.S, mu, s, mul_abcd(g0, u, gp));
+        for (int k = 0; k < 3 * NR; ++k) u.e[k / 3][k % 3] = mk<double>(p[k].x, p[k].y);
+        if constexpr (NR == 2) rebuild_row2(u);
+        store_link<double, NR>(L, g.S, mu, s, mul_abcd<NR>(g0, u, gp));
     }
 }
 
@@ -674,25 +678,35 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <class T>
-hipError_t launch_pack_links(const double *Uaos, void *L, long V, long S, hipStream_t st) {
-    k_pack_links<T><<<nblk(4 * V, 256), 256, 0, st>>>(reinterpret_cast<const double2 *>(Uaos),
-                                                      static_cast<vec2_t<T> *>(L), V, S);
+hipError_t launch_pack_links(const double *Uaos, void *L, long V, long S, int nr, hipStream_t st) {
+    auto U = reinterpret_cast<const double2 *>(Uaos);
+    auto Lp = static_cast<vec2_t<T> *>(L);
+    if (nr == 3) k_pack_links<T, 3><<<nblk(4 * V, 256), 256, 0, st>>>(U, Lp, V, S);
+    else k_pack_links<T, 2><<<nblk(4 * V, 256), 256, 0, st>>>(U, Lp, V, S);
     return hipGetLastError();
 }
-template hipError_t launch_pack_links<double>(const double *, void *, long, long, hipStream_t);
-template hipError_t launch_pack_links<float>(const double *, void *, long, long, hipStream_t);
+template hipError_t launch_pack_links<double>(const double *, void *, long, long, int,
+                                              hipStream_t);
+template hipError_t launch_pack_links<float>(const double *, void *, long, long, int, hipStream_t);
 
-hipError_t launch_unpack_links(const void *L64, double *Uaos, long V, long S, hipStream_t st) {
-    k_unpack_links<<<nblk(4 * V, 256), 256, 0, st>>>(static_cast<const double2 *>(L64),
-                                                     reinterpret_cast<double2 *>(Uaos), V, S);
+hipError_t launch_unpack_links(const void *L64, double *Uaos, long V, long S, int nr,
+                               hipStream_t st) {
+    auto Lp = static_cast<const double2 *>(L64);
+    auto U = reinterpret_cast<double2 *>(Uaos);
+    if (nr == 3) k_unpack_links<3><<<nblk(4 * V, 256), 256, 0, st>>>(Lp, U, V, S);
+    else k_unpack_links<2><<<nblk(4 * V, 256), 256, 0, st>>>(Lp, U, V, S);
     return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *partials,
                              dev_status *status, const fin_params &fp, hipStream_t st) {
-    k_div_reduce<T><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
-        g, static_cast<const vec2_t<T> *>(L), static_cast<vec2_t<T> *>(D), partials, status);
+    auto Lp = static_cast<const vec2_t<T> *>(L);
+    auto Dp = static_cast<vec2_t<T> *>(D);
+    if (g.nr == 3)
+        k_div_reduce<T, 3><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Lp, Dp, partials, status);
+    else
+        k_div_reduce<T, 2><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Lp, Dp, partials, status);
     if (fp.enabled) k_finalize<<<1, FIN_BLOCK, 0, st>>>(partials, site_blocks(g.V), status, fp);
     return hipGetLastError();
 }
@@ -711,13 +725,16 @@ hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void 
             static_cast<const vec2_t<T> *>(LD), static_cast<vec2_t<T> *>(Dout), Gp, c, partials,
             status);
     };
+    // G (the accumulated transformation) exists only in the FP32 phase
+    constexpr bool ACC = std::is_same<T, float>::value;
+    if ((G != nullptr) != ACC) return hipErrorInvalidValue;
     auto Gp = static_cast<vec2_t<T> *>(G);
-    if (G) {
-        if (exact) go(k_update<T, true, true>, Gp);
-        else go(k_update<T, true, false>, Gp);
+    if (g.nr == 3) {
+        if (exact) go(k_update<T, ACC, true, 3>, Gp);
+        else go(k_update<T, ACC, false, 3>, Gp);
     } else {
-        if (exact) go(k_update<T, false, true>, nullptr);
-        else go(k_update<T, false, false>, nullptr);
+        if (exact) go(k_update<T, ACC, true, 2>, Gp);
+        else go(k_update<T, ACC, false, 2>, Gp);
     }
     if (fp.enabled) k_finalize<<<1, FIN_BLOCK, 0, st>>>(partials, site_blocks(g.V), status, fp);
     return hipGetLastError();
@@ -758,9 +775,11 @@ hipError_t launch_g_identity(void *G32, long V, long S, hipStream_t st) {
 
 hipError_t launch_switch(const geom &g, const void *G32, const double *U0aos, void *L64,
                          hipStream_t st) {
-    k_switch<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, static_cast<const float2 *>(G32),
-                                                      reinterpret_cast<const double2 *>(U0aos),
-                                                      static_cast<double2 *>(L64));
+    auto Gp = static_cast<const float2 *>(G32);
+    auto U0 = reinterpret_cast<const double2 *>(U0aos);
+    auto Lp = static_cast<double2 *>(L64);
+    if (g.nr == 3) k_switch<3><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp);
+    else k_switch<2><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp);
     return hipGetLastError();
 }
 

@@ -104,6 +104,22 @@ def test_solve_32x4_exact_exp(lgf_gpu, configs, precision):
         assert abs(r.iterations - ref["iterations"]) <= 1
 
 
+def test_solve_32x4_link_format_18(lgf_gpu, configs):
+    """All three rows stored (no rebuild): the same solve as the 12-real form."""
+    ref = _golden()[0.45]
+    U = _config(configs, 0.45)
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, 0.08, 1e-15, max_iter=2000, link_format=18)
+    assert r.status == 0
+    out = Ug.cpu().numpy()
+    del Ug
+    assert oracle.theta(out) < 1e-15
+    assert abs(r.F - ref["F"]) <= 1e-12
+    assert abs(r.iterations - ref["iterations"]) <= 1
+    mu, md = oracle.unitarity(out)
+    assert mu <= 1e-13 and md <= 1e-13
+
+
 def test_lockstep_sweep_32x4_exact_exp(lgf_gpu, configs):
     with open(GOLDEN_EXP) as f:
         ref = json.load(f)["runs"][0]

@@ -186,3 +186,45 @@ def test_exact_exp_solve_matches_oracle(lgf_gpu, precision):
         assert abs(r.iterations - ref["iterations"]) <= 1
     first_order = oracle.fix(U, ALPHA, 1e-14, 1000)
     assert abs(r.F - first_order["F"]) < 1e-12
+
+
+# ------------------------------------------------------------ 18-real link storage
+
+@pytest.mark.parametrize("L,exact", [((4, 4, 4, 4), False), ((4, 6, 8, 12), False),
+                                     ((6, 6, 6, 6), True)])
+def test_link_format_18_lockstep(lgf_gpu, L, exact):
+    U, _ = inputs.make_config(L, 0.5, 80 + sum(L))
+    for step in range(3):
+        Ug = gpu(U)
+        lgf_gpu.iterate(Ug, ALPHA, 1, exact_exp=exact, link_format=18)
+        got = cpu(Ug)
+        ref = oracle.fix(U, ALPHA, 0.0, 1, exact_exp=exact)["U"]
+        assert np.max(np.abs(got - ref)) < 1e-13, step
+        U = got
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_link_format_18_solve(lgf_gpu, precision):
+    U, _ = inputs.make_config((8, 8, 8, 8), 0.5, inputs.CONFIG_SEEDS[("8^4", 0.5)])
+    ref = oracle.fix(U, ALPHA, 1e-14, 1000)
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, ALPHA, 1e-14, precision=precision, max_iter=1000, link_format=18)
+    assert r.status == 0
+    _check_solution(cpu(Ug), U, 1e-14, r.F)
+    assert abs(r.F - ref["F"]) < 1e-12
+    if precision == "fp64":
+        assert abs(r.iterations - ref["iterations"]) <= 1
+    # the context goes back to 12-real links and still agrees
+    Ug = gpu(U)
+    r12 = lgf_gpu.fix(Ug, ALPHA, 1e-14, precision=precision, max_iter=1000)
+    assert abs(r12.F - r.F) < 1e-13
+
+
+def test_link_format_rejects_other_sizes(lgf_gpu):
+    U = gpu(inputs.unit_config((4, 4, 4, 4)))
+    c = lgf_gpu._ctx(U)
+    for bad in (8, 9, 0, 24):
+        with pytest.raises(lgf_gpu.LgfError):
+            c.set_link_format(bad)
+    r = c.fix(U, ALPHA, 1e-15, 10)
+    assert r.status == 0 and r.iterations == 0

@@ -1,4 +1,4 @@
-"""Seeded synthetic SU(3) gauge-field inputs.
+"""Seeded synthetic SU(3) and SU(2) gauge-field inputs.
 
 This module only *makes inputs*: random near-identity link fields, Haar-random
 gauge transformations applied to them, tiny Abelian fields and random su(3)
@@ -14,7 +14,8 @@ The paper measures on Wilson-action ensembles at three unstated couplings; they
 are not available, so uncorrelated links ``U = exp(i*eps*sum_a h^a lambda_a/2)``
 with ``h^a ~ N(0,1)`` stand in for them, the disorder ``eps`` playing the role
 of the coupling.  A Haar-random gauge transformation is then applied so that
-the gauge-fixing problem is non-trivial.
+the gauge-fixing problem is non-trivial.  SU(2) fields (``*_su2``) are made the
+same way with the Pauli matrices, shape ``(4, Lt, Lz, Ly, Lx, 2, 2)``.
 """
 from __future__ import annotations
 
@@ -27,6 +28,7 @@ __all__ = [
     "GELL_MANN", "site_shape", "random_near_identity_links", "haar_su3",
     "apply_gauge_transformation", "make_config", "unit_config",
     "abelian_config", "random_omega", "CONFIG_SEEDS",
+    "PAULI", "haar_su2", "make_config_su2", "unit_config_su2", "abelian_config_su2",
 ]
 
 # Seeds per (lattice, disorder) workload, so every consumer draws the same field.
@@ -38,6 +40,9 @@ CONFIG_SEEDS = {
     ("4^4", 0.5): 4005,
     ("16^4", 0.5): 1605,
     ("48^3x96", 0.45): 4845,
+    ("su2 8^4", 0.5): 2801,
+    ("su2 16^4", 0.5): 2161,
+    ("su2 32^4", 0.45): 2324,
 }
 
 
@@ -179,3 +184,66 @@ def random_omega(L, sigma: float, seed: int) -> np.ndarray:
     """su(3) parameters omega^a(x) ~ N(0, sigma^2), shape (Lt, Lz, Ly, Lx, 8)."""
     rng = np.random.default_rng(seed)
     return sigma * rng.standard_normal(site_shape(L) + (8,))
+
+
+# ----------------------------------------------------------------------- SU(2)
+
+PAULI = np.array([[[0, 1], [1, 0]], [[0, -1j], [1j, 0]], [[1, 0], [0, -1]]],
+                 dtype=np.complex128)
+
+
+def _su2_from_quaternion(q: np.ndarray) -> np.ndarray:
+    """q0 + i (q1 s1 + q2 s2 + q3 s3) for unit quaternions q (..., 4)."""
+    out = np.empty(q.shape[:-1] + (2, 2), dtype=np.complex128)
+    out[..., 0, 0] = q[..., 0] + 1j * q[..., 3]
+    out[..., 0, 1] = q[..., 2] + 1j * q[..., 1]
+    out[..., 1, 0] = -q[..., 2] + 1j * q[..., 1]
+    out[..., 1, 1] = q[..., 0] - 1j * q[..., 3]
+    return out
+
+
+def random_near_identity_links_su2(L, eps: float, rng: np.random.Generator) -> np.ndarray:
+    """U_mu(x) = exp(i*eps*sum_a h^a sigma_a/2), h^a ~ N(0,1), in the closed form
+    cos(w) + i sin(w) (h/|h|).sigma with w = eps |h| / 2.  Draw order h[mu][t][z][y][x][a]."""
+    shp = (4,) + site_shape(L)
+    h = rng.standard_normal(shp + (3,))
+    nh = np.linalg.norm(h, axis=-1, keepdims=True)
+    w = 0.5 * eps * nh
+    q = np.concatenate([np.cos(w), np.sin(w) * h / np.where(nh > 0, nh, 1.0)], axis=-1)
+    return _su2_from_quaternion(q)
+
+
+def haar_su2(n: int, rng: np.random.Generator) -> np.ndarray:
+    """n Haar-distributed SU(2) matrices: unit quaternions from normalised
+    4-dimensional Gaussian vectors (uniform on the 3-sphere)."""
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=-1, keepdims=True)
+    return _su2_from_quaternion(q)
+
+
+def make_config_su2(L, eps: float, seed: int, haar: bool = True):
+    """SU(2) workload: near-identity links at disorder ``eps`` followed (if
+    ``haar``) by a Haar-random gauge transformation.  Returns ``(U, g)``."""
+    rng = np.random.default_rng(seed)
+    U = random_near_identity_links_su2(L, eps, rng)
+    g = None
+    if haar:
+        g = haar_su2(int(np.prod(site_shape(L))), rng).reshape(site_shape(L) + (2, 2))
+        U = apply_gauge_transformation(U, g)
+    return np.ascontiguousarray(U), g
+
+
+def unit_config_su2(L) -> np.ndarray:
+    U = np.zeros((4,) + site_shape(L) + (2, 2), dtype=np.complex128)
+    U[..., 0, 0] = U[..., 1, 1] = 1.0
+    return U
+
+
+def abelian_config_su2(L, amp: float, seed: int) -> np.ndarray:
+    """Tiny field in the sigma_3 direction: U_mu(x) = diag(e^{i phi/2}, e^{-i phi/2})."""
+    rng = np.random.default_rng(seed)
+    phi = amp * rng.standard_normal((4,) + site_shape(L))
+    U = np.zeros((4,) + site_shape(L) + (2, 2), dtype=np.complex128)
+    U[..., 0, 0] = np.exp(0.5j * phi)
+    U[..., 1, 1] = np.exp(-0.5j * phi)
+    return U

@@ -27,6 +27,7 @@ L = (32, 32, 32, 32)
 EPS_ALL = (0.6, 0.45, 0.35)
 EPS_MAIN = 0.45
 BYTES_UPDATE_18 = 4 * 144 * 2 + 128  # update with 18-real links: R+W 4 x 144 B, R+W 64 B
+BYTES_UPDATE_SU2 = 4 * 32 * 2 + 32 * 2  # SU(2) update: R+W 4 links x 32 B, R+W 2 fields
 SD_TOL = 1e-10  # plain steepest descent needs thousands of sweeps at 32^4
 # algorithmic bytes per site of each sweep kernel (FP64 / FP32 with G)
 BYTES_PER_SITE = {
@@ -104,6 +105,12 @@ def main() -> int:
     if os.path.exists(gpath):
         with open(gpath) as f:
             golden_exp = json.load(f)["runs"][0]
+
+    golden_su2 = None
+    gpath = os.path.join(ROOT, "tests", "golden", "oracle_su2324.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            golden_su2 = json.load(f)["runs"][0]
 
     def golden_iters_at(tol):
         """Accelerated (oracle) sweeps until theta < tol on the main input."""
@@ -236,6 +243,42 @@ def main() -> int:
         "solve_ms": round(1e3 * float(np.median(times)), 3), "iterations": res.iterations,
         "F": res.F, "dF_vs_oracle": abs(res.F - golden[EPS_MAIN]["F"]) if golden else None}
     log(f"18-real links: {variants['link18/fp64']}")
+    # SU(2) on the same lattice (N_c = 2; links stored as row 0)
+    U2 = inputs.make_config_su2(L, EPS_MAIN, inputs.CONFIG_SEEDS[("su2 32^4", EPS_MAIN)])[0]
+    U2 = torch.from_numpy(U2).to("cuda")
+    w2 = torch.empty_like(U2)
+    c2 = lgf.Context(L, "fp64", nc=2)
+    w2.copy_(U2)
+    c2.iterate(w2, ALPHA, args.warmup)
+    w2.copy_(U2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c2.iterate(w2, ALPHA, args.steps)
+    torch.cuda.synchronize()
+    ips2 = args.steps / (time.perf_counter() - t0)
+    prof2 = c2.profile(U2, ALPHA, 20)
+    times = []
+    for _ in range(args.solves):
+        w2.copy_(U2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = c2.fix(w2, ALPHA, TOL, 2000)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    entry = {"sweeps_per_s": round(ips2, 1),
+             "per_kernel_ms": {k: round(v, 5) for k, v in prof2.items()},
+             "update_GBps": round(BYTES_UPDATE_SU2 * V / (prof2["update"] * 1e-3) / 1e9, 1),
+             "update_bytes_per_site": BYTES_UPDATE_SU2,
+             "solve_ms": round(1e3 * float(np.median(times)), 3), "iterations": res.iterations,
+             "status": res.status, "F": res.F}
+    if golden_su2:
+        entry["dF_vs_oracle"] = abs(res.F - golden_su2["F"])
+        entry["oracle_iterations"] = golden_su2["iterations"]
+    variants["su2/fp64"] = entry
+    log(f"SU(2): {entry}")
+    c2.close()
+    del U2, w2
+
     ctx64.set_acceleration(False)
     work.copy_(U0)
     torch.cuda.synchronize()

@@ -86,6 +86,17 @@ typedef struct {
  * HIP device at creation is the context's device.  *out receives the context. */
 int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream);
 
+/* As lgf_create for the gauge group SU(nc), nc = 3 or 2 (the paper's
+ * functional is written for a general N_c: F = 1/(Nd Nc V) sum Re Tr[...],
+ * theta = 1/(Nc V) sum Tr[Delta Delta^+]).  lgf_create(...) is
+ * lgf_create_group(..., 3, ...).  SU(2) contexts take links of shape
+ * [4][Lt][Lz][Ly][Lx][2][2] complex128, store row 0 of each link (an SU(2)
+ * matrix is [[a, b], [-conj(b), conj(a)]]) and run lgf_fix, lgf_iterate,
+ * lgf_theta, lgf_functional (g == NULL), lgf_profile and the step options in
+ * LGF_FP64; the other entry points return LGF_ERR_ARG for them, and so does
+ * precision LGF_MIXED. */
+int lgf_create_group(lgf_ctx **out, const int L[4], int nc, int precision, void *stream);
+
 /* Free the context's device scratch; NULL is ignored. */
 void lgf_destroy(lgf_ctx *ctx);
 

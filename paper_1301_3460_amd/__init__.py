@@ -83,6 +83,8 @@ def load(path: str | None = None):
     vp, dp, ip = c.c_void_p, c.POINTER(c.c_double), c.POINTER(c.c_int)
     sigs = {
         "lgf_create": (c.c_int, [c.POINTER(vp), c.POINTER(c.c_int * 4), c.c_int, vp]),
+        "lgf_create_group": (c.c_int, [c.POINTER(vp), c.POINTER(c.c_int * 4), c.c_int, c.c_int,
+                                       vp]),
         "lgf_destroy": (None, [vp]),
         "lgf_set_theta_switch": (c.c_int, [vp, c.c_double]),
         "lgf_set_acceleration": (c.c_int, [vp, c.c_int]),
@@ -112,8 +114,9 @@ def load(path: str | None = None):
 
 
 def _lattice_of_links(U) -> tuple:
-    if U.dim() != 7 or U.shape[0] != 4 or tuple(U.shape[-2:]) != (3, 3):
-        raise ValueError(f"links must have shape (4, Lt, Lz, Ly, Lx, 3, 3), got {tuple(U.shape)}")
+    if U.dim() != 7 or U.shape[0] != 4 or tuple(U.shape[-2:]) not in ((3, 3), (2, 2)):
+        raise ValueError("links must have shape (4, Lt, Lz, Ly, Lx, N, N) with N = 3 or 2, "
+                         f"got {tuple(U.shape)}")
     Lt, Lz, Ly, Lx = (int(v) for v in U.shape[1:5])
     return (Lx, Ly, Lz, Lt)
 
@@ -133,13 +136,15 @@ def _check(t, dtype, shape=None, name="tensor"):
 
 
 class Context:
-    """A library context for one lattice shape, precision, device and stream."""
+    """A library context for one lattice shape, gauge group SU(nc), precision,
+    device and stream."""
 
-    def __init__(self, L, precision: str = "fp64", stream=None):
+    def __init__(self, L, precision: str = "fp64", stream=None, nc: int = 3):
         import torch
 
         lib = load()
         self.L = tuple(int(v) for v in L)
+        self.nc = int(nc)
         self.precision = precision
         prec = {"fp64": LGF_FP64, "mixed": LGF_MIXED}[precision]
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -147,8 +152,8 @@ class Context:
         arr = (ctypes.c_int * 4)(*self.L)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            rc = lib.lgf_create(ctypes.byref(h), ctypes.byref(arr), prec,
-                                ctypes.c_void_p(self.stream.cuda_stream))
+            rc = lib.lgf_create_group(ctypes.byref(h), ctypes.byref(arr), self.nc, prec,
+                                      ctypes.c_void_p(self.stream.cuda_stream))
         if rc != LGF_OK:
             raise LgfError(rc, lib.lgf_last_error(None).decode())
         self._h = h
@@ -175,7 +180,7 @@ class Context:
     def _links(self, U, name="U"):
         import torch
 
-        return _check(U, torch.complex128, (4,) + self._site_shape() + (3, 3), name)
+        return _check(U, torch.complex128, (4,) + self._site_shape() + (self.nc, self.nc), name)
 
     def set_acceleration(self, on: bool):
         """True: Fourier-accelerated steepest descent; False: plain steepest descent."""
@@ -336,21 +341,21 @@ class Context:
 _contexts: dict = {}
 
 
-def _ctx_for(L, device, precision="fp64") -> Context:
-    """Cached context for lattice L on `device`'s current stream."""
+def _ctx_for(L, device, precision="fp64", nc=3) -> Context:
+    """Cached context for lattice L and SU(nc) on `device`'s current stream."""
     import torch
 
     stream = torch.cuda.current_stream(device)
-    key = (tuple(L), precision, stream.device.index, stream.cuda_stream)
+    key = (tuple(L), nc, precision, stream.device.index, stream.cuda_stream)
     c = _contexts.get(key)
     if c is None:
-        c = Context(L, precision, stream)
+        c = Context(L, precision, stream, nc)
         _contexts[key] = c
     return c
 
 
 def _ctx(U, precision="fp64") -> Context:
-    return _ctx_for(_lattice_of_links(U), U.device, precision)
+    return _ctx_for(_lattice_of_links(U), U.device, precision, int(U.shape[-1]))
 
 
 def fix(U, alpha=0.08, theta_tol=1e-15, precision="fp64", max_iter=10000, theta_switch=1e-8,
@@ -364,7 +369,8 @@ def fix(U, alpha=0.08, theta_tol=1e-15, precision="fp64", max_iter=10000, theta_
         c.set_theta_switch(theta_switch)
     c.set_acceleration(accelerate)
     c.set_exponential(exact_exp)
-    c.set_link_format(link_format)
+    if c.nc == 3 or link_format != 12:
+        c.set_link_format(link_format)
     return c.fix(U, alpha, theta_tol, max_iter)
 
 
@@ -373,7 +379,8 @@ def iterate(U, alpha=0.08, n=1, precision="fp64", accelerate=True, exact_exp=Fal
     c = _ctx(U, precision)
     c.set_acceleration(accelerate)
     c.set_exponential(exact_exp)
-    c.set_link_format(link_format)
+    if c.nc == 3 or link_format != 12:
+        c.set_link_format(link_format)
     return c.iterate(U, alpha, n)
 
 

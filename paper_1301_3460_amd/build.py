@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblgf.so")
 SOURCES = [os.path.join(CSRC, f) for f in
-           ("sweep.hip", "fft_f64.hip", "fft_f32.hip", "api.cpp")]
+           ("sweep.hip", "su2.hip", "fft_f64.hip", "fft_f32.hip", "api.cpp")]
 ARCH = os.environ.get("LGF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

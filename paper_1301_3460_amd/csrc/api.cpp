@@ -86,8 +86,9 @@ int fail(lgf_ctx *c, int code, const std::string &msg) {
                         std::string(#expr) + ": " + hipGetErrorString(e_));                   \
     } while (0)
 
-double normF(const lgf_ctx *c) { return 1.0 / (4.0 * 3.0 * (double)c->g.V); }
-double normT(const lgf_ctx *c) { return 1.0 / (3.0 * (double)c->g.V); }
+// F = normF sum Re Tr U, theta = normT sum Tr[Delta Delta^+] (Nd = 4, Nc = g.nc)
+double normF(const lgf_ctx *c) { return 1.0 / (4.0 * c->g.nc * (double)c->g.V); }
+double normT(const lgf_ctx *c) { return 1.0 / ((double)c->g.nc * (double)c->g.V); }
 
 // Stopping-test parameters for the sweep kernels (enabled == false: the
 // kernel only writes block partials).
@@ -248,14 +249,14 @@ geom g12(const lgf_ctx *c) {
 }
 
 // (Re)allocate the working link buffers for the context's link format: each
-// holds 4 links x 3*nr complex entries per site (FP64); the FP32 pair aliases
-// the second buffer.
+// holds 4 links x (3*nr for SU(3), 2 for SU(2)) complex entries per site
+// (FP64); the FP32 pair aliases the second buffer.
 bool alloc_links(lgf_ctx *c) {
     for (auto &p : c->L64) {
         if (p) (void)hipFree(p);
         p = nullptr;
     }
-    const size_t n = (size_t)12 * c->g.nr * c->g.S;
+    const size_t n = (size_t)4 * (c->g.nc == 2 ? 2 : 3 * c->g.nr) * c->g.S;
     for (auto &p : c->L64)
         if (hipMalloc((void **)&p, n * sizeof(double2)) != hipSuccess) return false;
     c->L32[0] = reinterpret_cast<float2 *>(c->L64[1]);
@@ -273,7 +274,7 @@ int check_ctx(lgf_ctx *c) {
 
 // Pack caller links into FP64 working buffer 0, then F/theta of them.
 int eval_links64(lgf_ctx *c, const double *U, double &F, double &theta) {
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->g.nr, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<double>(c->g, c->L64[0], c->D64[0], c->partials, c->status,
                                         finp(c, false), c->stream));
@@ -312,7 +313,7 @@ template <class T>
 int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
     using P = prec<T>;
     const bool accG = std::is_same<T, float>::value;
-    HIPCHK(c, launch_pack_links<T>(U, P::links(c, 0), c->g.V, c->g.S, c->g.nr, c->stream));
+    HIPCHK(c, launch_pack_links<T>(U, P::links(c, 0), c->g, c->stream));
     if (accG) HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->g.S, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<T>(c->g, P::links(c, 0), P::field(c, 0), c->partials, c->status,
@@ -366,8 +367,15 @@ int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
 extern "C" {
 
 int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
+    return lgf_create_group(out, L, 3, precision, stream);
+}
+
+int lgf_create_group(lgf_ctx **out, const int L[4], int nc, int precision, void *stream) {
     if (!out || !L) return fail(nullptr, LGF_ERR_ARG, "null argument");
     *out = nullptr;
+    if (nc != 2 && nc != 3) return fail(nullptr, LGF_ERR_ARG, "gauge group must be SU(2) or SU(3)");
+    if (nc == 2 && precision != LGF_FP64)
+        return fail(nullptr, LGF_ERR_ARG, "SU(2) contexts run in LGF_FP64 only");
     if (!shape_ok(L))
         return fail(nullptr, LGF_ERR_ARG,
                     "unsupported lattice extent (allowed: 2 3 4 6 8 12 16 24 32 48 64 96 128)");
@@ -387,6 +395,8 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
     c->g.Lt = L[3];
     c->g.V = (long)L[0] * L[1] * L[2] * L[3];
     c->g.S = c->g.V + SOA_PAD;
+    c->g.nc = nc;
+    c->g.nf = nc == 3 ? 4 : 2;
     // 64 consecutive xy-sites x 4 t per block where the shape allows it (8x8
     // xy tiles keep more neighbours in a block, but their short rows cost more
     // in DRAM efficiency than they save)
@@ -407,8 +417,8 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream) {
     bool ok = true;
     const long S = c->g.S;
     ok = ok && alloc_links(c);
-    ok = ok && alloc((void **)&c->D64[0], (size_t)4 * S * sizeof(double2));
-    ok = ok && alloc((void **)&c->D64[1], (size_t)4 * S * sizeof(double2));
+    ok = ok && alloc((void **)&c->D64[0], (size_t)c->g.nf * S * sizeof(double2));
+    ok = ok && alloc((void **)&c->D64[1], (size_t)c->g.nf * S * sizeof(double2));
     if (precision == LGF_MIXED) ok = ok && alloc((void **)&c->G32, (size_t)6 * S * sizeof(float2));
     ok = ok && alloc((void **)&c->tw64, TW_M * sizeof(double2));
     ok = ok && alloc((void **)&c->tw32, TW_M * sizeof(float2));
@@ -477,6 +487,7 @@ int lgf_set_acceleration(lgf_ctx *c, int on) {
 int lgf_set_link_format(lgf_ctx *c, int nreal) {
     if (!c) return LGF_ERR_ARG;
     if (nreal != 12 && nreal != 18) return fail(c, LGF_ERR_ARG, "link format must be 12 or 18");
+    if (c->g.nc != 3) return fail(c, LGF_ERR_ARG, "link formats apply to SU(3) contexts");
     const int nr = nreal / 6;
     if (nr == c->g.nr) return LGF_OK;
     if (hipSetDevice(c->device) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
@@ -511,7 +522,7 @@ static int solve(lgf_ctx *c, double *U, double alpha, double tol, int max_iter, 
     int cur64 = 0;
     if (c->precision == LGF_MIXED) {
         // FP32 phase on a downcast copy; G accumulates the applied transformation
-        HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g.V, c->g.S, c->g.nr, c->stream));
+        HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g, c->stream));
         HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->g.S, c->stream));
         const double tol32 = std::max(tol, c->theta_switch);
         rc = run_phase<float>(c, alpha, tol32, max_iter, true, 0, st);
@@ -528,14 +539,14 @@ static int solve(lgf_ctx *c, double *U, double alpha, double tol, int max_iter, 
             cur64 = n64 & 1;
         }
     } else {
-        HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->g.nr, c->stream));
+        HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g, c->stream));
         rc = run_phase<double>(c, alpha, tol, max_iter, false, 0, st);
         if (rc) return rc;
         n64 = st.n;
         code = st.code;
         cur64 = n64 & 1;
     }
-    HIPCHK(c, launch_unpack_links(c->L64[cur64], U, c->g.V, c->g.S, c->g.nr, c->stream));
+    HIPCHK(c, launch_unpack_links(c->L64[cur64], U, c->g, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->hist_len = n32 + n64 + 1;
     const int out = status_to_code(code);
@@ -574,20 +585,20 @@ int lgf_iterate(lgf_ctx *c, double *U, double alpha, int n_iter, lgf_result *res
     dev_status st{};
     int n32 = 0, n64 = 0, cur64 = 0;
     if (c->precision == LGF_MIXED) {
-        HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g.V, c->g.S, c->g.nr, c->stream));
+        HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g, c->stream));
         HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->g.S, c->stream));
         rc = run_phase<float>(c, alpha, 0.0, n_iter, true, 0, st);
         if (rc) return rc;
         n32 = st.n;
         HIPCHK(c, launch_switch(c->g, c->G32, U, c->L64[0], c->stream));
     } else {
-        HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->g.nr, c->stream));
+        HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g, c->stream));
         rc = run_phase<double>(c, alpha, 0.0, n_iter, false, 0, st);
         if (rc) return rc;
         n64 = st.n;
         cur64 = n64 & 1;
     }
-    HIPCHK(c, launch_unpack_links(c->L64[cur64], U, c->g.V, c->g.S, c->g.nr, c->stream));
+    HIPCHK(c, launch_unpack_links(c->L64[cur64], U, c->g, c->stream));
     double F = st.F, th = st.theta;
     if (c->precision == LGF_MIXED) {
         rc = eval_links64(c, U, F, th);
@@ -609,6 +620,7 @@ int lgf_iterate(lgf_ctx *c, double *U, double alpha, int n_iter, lgf_result *res
 
 int lgf_functional(lgf_ctx *c, const double *U, const double *g, double *F) {
     if (!c) return LGF_ERR_ARG;
+    if (g && c->g.nc != 3) return fail(c, LGF_ERR_ARG, "F_U[g] with g is available for SU(3) only");
     if (!U || !F) return fail(c, LGF_ERR_ARG, "null argument");
     int rc = check_ctx(c);
     if (rc) return rc;
@@ -616,7 +628,7 @@ int lgf_functional(lgf_ctx *c, const double *U, const double *g, double *F) {
         double th;
         return eval_links64(c, U, *F, th);
     }
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, 2, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], g12(c), c->stream));
     HIPCHK(c, launch_functional_g(c->g, c->L64[0], g, c->partials, c->stream));
     double A, B;
     rc = sum_partials(c, A, B);
@@ -636,10 +648,11 @@ int lgf_theta(lgf_ctx *c, const double *U, double *theta) {
 
 int lgf_plaquette(lgf_ctx *c, const double *U, double *P) {
     if (!c) return LGF_ERR_ARG;
+    if (c->g.nc != 3) return fail(c, LGF_ERR_ARG, "the plaquette is available for SU(3) only");
     if (!U || !P) return fail(c, LGF_ERR_ARG, "null argument");
     int rc = check_ctx(c);
     if (rc) return rc;
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, 2, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], g12(c), c->stream));
     HIPCHK(c, launch_plaquette(c->g, c->L64[0], c->partials, c->stream));
     double A, B;
     rc = sum_partials(c, A, B);
@@ -650,10 +663,11 @@ int lgf_plaquette(lgf_ctx *c, const double *U, double *P) {
 
 int lgf_divergence(lgf_ctx *c, const double *U, double *Delta) {
     if (!c) return LGF_ERR_ARG;
+    if (c->g.nc != 3) return fail(c, LGF_ERR_ARG, "lgf_divergence is available for SU(3) only");
     if (!U || !Delta) return fail(c, LGF_ERR_ARG, "null argument");
     int rc = check_ctx(c);
     if (rc) return rc;
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, c->g.nr, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<double>(c->g, c->L64[0], c->D64[0], c->partials, c->status,
                                         finp(c, false), c->stream));
@@ -664,6 +678,7 @@ int lgf_divergence(lgf_ctx *c, const double *U, double *Delta) {
 
 int lgf_fourier_accelerate(lgf_ctx *c, const double *D, double *LD) {
     if (!c) return LGF_ERR_ARG;
+    if (c->g.nc != 3) return fail(c, LGF_ERR_ARG, "lgf_fourier_accelerate is available for SU(3) only");
     if (!D || !LD) return fail(c, LGF_ERR_ARG, "null argument");
     int rc = check_ctx(c);
     if (rc) return rc;
@@ -680,6 +695,7 @@ int lgf_fourier_accelerate(lgf_ctx *c, const double *D, double *LD) {
 
 int lgf_fft4d(lgf_ctx *c, double *fields, int sign) {
     if (!c) return LGF_ERR_ARG;
+    if (c->g.nc != 3) return fail(c, LGF_ERR_ARG, "lgf_fft4d is available for SU(3) only");
     if (!fields || (sign != 1 && sign != -1)) return fail(c, LGF_ERR_ARG, "bad argument");
     int rc = check_ctx(c);
     if (rc) return rc;
@@ -710,6 +726,7 @@ int lgf_fft4d(lgf_ctx *c, double *fields, int sign) {
 
 int lgf_functional_omega(lgf_ctx *c, const double *U, const double *omega, double *F) {
     if (!c) return LGF_ERR_ARG;
+    if (c->g.nc != 3) return fail(c, LGF_ERR_ARG, "the omega parametrisation is available for SU(3) only");
     if (!U || !omega || !F) return fail(c, LGF_ERR_ARG, "null argument");
     int rc = check_ctx(c);
     if (rc) return rc;
@@ -721,12 +738,13 @@ int lgf_functional_omega(lgf_ctx *c, const double *U, const double *omega, doubl
 int lgf_functional_omega_grad(lgf_ctx *c, const double *U, const double *omega, double *F,
                               double *dF) {
     if (!c) return LGF_ERR_ARG;
+    if (c->g.nc != 3) return fail(c, LGF_ERR_ARG, "the omega parametrisation is available for SU(3) only");
     if (!U || !omega || !F || !dF) return fail(c, LGF_ERR_ARG, "null argument");
     int rc = check_ctx(c);
     if (rc) return rc;
     if ((rc = ensure_diff_scratch(c))) return rc;
     HIPCHK(c, launch_expm_sites(omega, c->gaos, c->g.V, c->stream));
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, 2, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], g12(c), c->stream));
     HIPCHK(c, launch_rotate_links(c->g, c->L64[0], c->gaos, c->Lrot, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<double>(g12(c), c->Lrot, c->D64[0], c->partials, c->status,
@@ -742,11 +760,12 @@ int lgf_functional_omega_grad(lgf_ctx *c, const double *U, const double *omega, 
 
 int lgf_theta_grad(lgf_ctx *c, const double *U, const double *eps, double *theta, double *dtheta) {
     if (!c) return LGF_ERR_ARG;
+    if (c->g.nc != 3) return fail(c, LGF_ERR_ARG, "the theta gradient is available for SU(3) only");
     if (!U || !theta) return fail(c, LGF_ERR_ARG, "null argument");
     int rc = check_ctx(c);
     if (rc) return rc;
     if ((rc = ensure_diff_scratch(c))) return rc;
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g.V, c->g.S, 2, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], g12(c), c->stream));
     const void *Lw = c->L64[0];
     if (eps) {
         HIPCHK(c, launch_expm_sites(eps, c->gaos, 4 * c->g.V, c->stream));

@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(rc_max_threads<T>())
     MACRO(2) MACRO(3) MACRO(4) MACRO(6) MACRO(8) MACRO(12) MACRO(16) MACRO(24) MACRO(32)
 
 template <class T> inline int xy_fields_per_block(const geom &g) {
-    int F = 4;
+    int F = g.nf;
     while (F > 1 && F * g.Lx > rc_max_threads<T>()) F >>= 1;
     return F;
 }
@@ -358,7 +358,7 @@ hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const 
     const size_t lds = fft_xy_lds_bytes<T>(g);
     if (xy_use_rc<T>(g)) {
         const int F = xy_fields_per_block<T>(g);
-        dim3 grid((unsigned)(g.Lz * g.Lt), 4 / F);
+        dim3 grid((unsigned)(g.Lz * g.Lt), (unsigned)(g.nf / F));
         const unsigned nt = (unsigned)(F * g.Lx);
 #define LGF_XY(NN)                                                                            \
     case NN:                                                                                  \
@@ -372,7 +372,7 @@ hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const 
 #undef LGF_XY
         return hipGetLastError();
     }
-    dim3 grid((unsigned)(g.Lz * g.Lt), 4);
+    dim3 grid((unsigned)(g.Lz * g.Lt), (unsigned)g.nf);
     if (dir < 0) k_fft_xy<T, -1><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
     else k_fft_xy<T, +1><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
     return hipGetLastError();
@@ -439,7 +439,7 @@ hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const
                          hipStream_t st) {
     const long Lxy = (long)g.Lx * g.Ly;
     const int W = pl.W;
-    dim3 grid((unsigned)((Lxy + W - 1) / W), 4);
+    dim3 grid((unsigned)((Lxy + W - 1) / W), (unsigned)g.nf);
     auto Dp = static_cast<vec2_t<T> *>(D);
     auto twp = static_cast<const vec2_t<T> *>(tw);
     if (pl.rc) {

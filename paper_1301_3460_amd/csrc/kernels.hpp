@@ -49,6 +49,9 @@ struct geom {
     int tblock = 0, sgroup = 1;
     // stored rows per working link: 2 (12-real, row 2 rebuilt) or 3 (18-real)
     int nr = 2;
+    // gauge group SU(nc), nc = 3 or 2, and the number of complex Fourier
+    // fields carrying Delta (4 for SU(3), 2 for SU(2))
+    int nc = 3, nf = 4;
 };
 
 constexpr int SITE_BLOCK = 256;  // threads per block of the site kernels
@@ -56,9 +59,8 @@ inline int site_blocks(long V) { return (int)((V + SITE_BLOCK - 1) / SITE_BLOCK)
 
 // All launchers enqueue on `st` and return hipGetLastError().
 template <class T>
-hipError_t launch_pack_links(const double *Uaos, void *L, long V, long S, int nr, hipStream_t st);
-hipError_t launch_unpack_links(const void *L64, double *Uaos, long V, long S, int nr,
-                               hipStream_t st);
+hipError_t launch_pack_links(const double *Uaos, void *L, const geom &g, hipStream_t st);
+hipError_t launch_unpack_links(const void *L64, double *Uaos, const geom &g, hipStream_t st);
 
 template <class T>
 hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *partials,
@@ -120,5 +122,18 @@ hipError_t launch_omega_grad(const geom &g, const void *D64, const double *omega
                              double normF, hipStream_t st);
 hipError_t launch_theta_grad(const geom &g, const void *L64, const void *D64, const double *eps,
                              double *dth, double normT, hipStream_t st);
+
+// SU(2) kernels (su2.hip); the generic launchers above dispatch to them when
+// g.nc == 2.
+template <class T>
+hipError_t launch_pack_su2(const double *Uaos, void *L, const geom &g, hipStream_t st);
+hipError_t launch_unpack_su2(const void *L64, double *Uaos, const geom &g, hipStream_t st);
+template <class T>
+hipError_t launch_div_reduce_su2(const geom &g, const void *L, void *D, double *partials,
+                                 dev_status *status, hipStream_t st);
+template <class T>
+hipError_t launch_update_su2(const geom &g, const void *Lin, void *Lout, const void *LD,
+                             void *Dout, T c, bool exact, double *partials, dev_status *status,
+                             hipStream_t st);
 
 }  // namespace lgf

@@ -678,22 +678,24 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <class T>
-hipError_t launch_pack_links(const double *Uaos, void *L, long V, long S, int nr, hipStream_t st) {
+hipError_t launch_pack_links(const double *Uaos, void *L, const geom &g, hipStream_t st) {
+    if (g.nc == 2) return launch_pack_su2<T>(Uaos, L, g, st);
     auto U = reinterpret_cast<const double2 *>(Uaos);
     auto Lp = static_cast<vec2_t<T> *>(L);
-    if (nr == 3) k_pack_links<T, 3><<<nblk(4 * V, 256), 256, 0, st>>>(U, Lp, V, S);
+    const long V = g.V, S = g.S;
+    if (g.nr == 3) k_pack_links<T, 3><<<nblk(4 * V, 256), 256, 0, st>>>(U, Lp, V, S);
     else k_pack_links<T, 2><<<nblk(4 * V, 256), 256, 0, st>>>(U, Lp, V, S);
     return hipGetLastError();
 }
-template hipError_t launch_pack_links<double>(const double *, void *, long, long, int,
-                                              hipStream_t);
-template hipError_t launch_pack_links<float>(const double *, void *, long, long, int, hipStream_t);
+template hipError_t launch_pack_links<double>(const double *, void *, const geom &, hipStream_t);
+template hipError_t launch_pack_links<float>(const double *, void *, const geom &, hipStream_t);
 
-hipError_t launch_unpack_links(const void *L64, double *Uaos, long V, long S, int nr,
-                               hipStream_t st) {
+hipError_t launch_unpack_links(const void *L64, double *Uaos, const geom &g, hipStream_t st) {
+    if (g.nc == 2) return launch_unpack_su2(L64, Uaos, g, st);
     auto Lp = static_cast<const double2 *>(L64);
     auto U = reinterpret_cast<double2 *>(Uaos);
-    if (nr == 3) k_unpack_links<3><<<nblk(4 * V, 256), 256, 0, st>>>(Lp, U, V, S);
+    const long V = g.V, S = g.S;
+    if (g.nr == 3) k_unpack_links<3><<<nblk(4 * V, 256), 256, 0, st>>>(Lp, U, V, S);
     else k_unpack_links<2><<<nblk(4 * V, 256), 256, 0, st>>>(Lp, U, V, S);
     return hipGetLastError();
 }
@@ -703,7 +705,10 @@ hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *part
                              dev_status *status, const fin_params &fp, hipStream_t st) {
     auto Lp = static_cast<const vec2_t<T> *>(L);
     auto Dp = static_cast<vec2_t<T> *>(D);
-    if (g.nr == 3)
+    if (g.nc == 2) {
+        const hipError_t e = launch_div_reduce_su2<T>(g, L, D, partials, status, st);
+        if (e != hipSuccess) return e;
+    } else if (g.nr == 3)
         k_div_reduce<T, 3><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Lp, Dp, partials, status);
     else
         k_div_reduce<T, 2><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Lp, Dp, partials, status);
@@ -729,7 +734,15 @@ hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void 
     constexpr bool ACC = std::is_same<T, float>::value;
     if ((G != nullptr) != ACC) return hipErrorInvalidValue;
     auto Gp = static_cast<vec2_t<T> *>(G);
-    if (g.nr == 3) {
+    if (g.nc == 2) {
+        // SU(2) runs in FP64 only (the context refuses mixed precision)
+        if constexpr (ACC) return hipErrorInvalidValue;
+        else {
+            const hipError_t e =
+                launch_update_su2<T>(g, Lin, Lout, LD, Dout, c, exact, partials, status, st);
+            if (e != hipSuccess) return e;
+        }
+    } else if (g.nr == 3) {
         if (exact) go(k_update<T, ACC, true, 3>, Gp);
         else go(k_update<T, ACC, false, 3>, Gp);
     } else {

@@ -20,6 +20,7 @@ sys.path.insert(0, ROOT)
 
 import inputs  # noqa: E402
 import oracle  # noqa: E402
+from oracle import su2  # noqa: E402
 
 WORKLOADS = {
     "32^4": {"L": (32, 32, 32, 32), "eps": [0.6, 0.45, 0.35], "alpha": 0.08, "tol": 1e-15},
@@ -28,6 +29,9 @@ WORKLOADS = {
     # the same 32^4 input, solved with the exactly exponentiated step
     "32^4-exp": {"L": (32, 32, 32, 32), "eps": [0.45], "alpha": 0.08, "tol": 1e-15,
                  "seeds": "32^4", "exact_exp": True},
+    # SU(2) (the numpy SU(2) oracle)
+    "su2 32^4": {"L": (32, 32, 32, 32), "eps": [0.45], "alpha": 0.08, "tol": 1e-15,
+                 "group": "su2"},
 }
 
 
@@ -38,15 +42,18 @@ def main(name: str) -> None:
            "exact_exp": exact, "threads": oracle.get_threads(), "runs": []}
     for eps in w["eps"]:
         seed = inputs.CONFIG_SEEDS[(w.get("seeds", name), eps)]
-        U, _ = inputs.make_config(w["L"], eps, seed)
-        P0 = oracle.plaquette(U)
+        is_su2 = w.get("group") == "su2"
+        make = inputs.make_config_su2 if is_su2 else inputs.make_config
+        orc = su2 if is_su2 else oracle
+        U, _ = make(w["L"], eps, seed)
+        P0 = orc.plaquette(U)
         t0 = time.time()
-        r = oracle.fix(U, w["alpha"], w["tol"], 2000, exact_exp=exact)
+        r = orc.fix(U, w["alpha"], w["tol"], 2000, exact_exp=exact)
         dt = time.time() - t0
-        mu, md = oracle.unitarity(r["U"])
+        mu, md = orc.unitarity(r["U"])
         run = {"eps": eps, "seed": seed, "status": r["status"], "iterations": r["iterations"],
                "F": r["F"], "theta": r["theta"], "plaquette_in": P0,
-               "plaquette_out": oracle.plaquette(r["U"]), "unitarity": mu, "det": md,
+               "plaquette_out": orc.plaquette(r["U"]), "unitarity": mu, "det": md,
                "F_hist": list(r["F_hist"]), "theta_hist": list(r["theta_hist"]),
                "seconds": dt}
         print(f"{name} eps={eps}: {r['iterations']} it, F={r['F']:.15f}, theta={r['theta']:.3e}, "
@@ -54,7 +61,7 @@ def main(name: str) -> None:
         out["runs"].append(run)
         del U, r
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                        f"oracle_{name.replace('^', '').replace('-', '')}.json")
+                        f"oracle_{name.replace('^', '').replace('-', '').replace(' ', '')}.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path)

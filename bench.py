@@ -216,6 +216,26 @@ def main() -> int:
         ctx.set_exponential(False)
         variants[f"exact_exp/{prec}"] = entry
         log(f"exact exponential {prec}: {entry}")
+    # later hand-over points of the mixed solve (FP32 sweeps further down)
+    for sw in (1e-9, 1e-10, 1e-11):
+        ctx32.set_theta_switch(sw)
+        times = []
+        for _ in range(args.solves):
+            work.copy_(U0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = ctx32.fix(work, ALPHA, TOL, 2000)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        e = {"ms": round(1e3 * float(np.median(times)), 3), "iterations": res.iterations,
+             "fp32_iterations": res.fp32_iterations, "status": res.status, "F": res.F,
+             "theta": res.theta}
+        if golden:
+            e["dF_vs_oracle"] = abs(res.F - golden[EPS_MAIN]["F"])
+        variants[f"mixed_switch_{sw:g}"] = e
+        log(f"mixed, switch at {sw:g}: {e}")
+    ctx32.set_theta_switch(1e-8)
+
     # 18-real working links (all three rows stored) against the 12-real default
     ctx64.set_link_format(18)
     work.copy_(U0)

@@ -23,6 +23,7 @@ thread_local std::string g_create_error;
 
 constexpr int HIST_CAP = 1 << 16;
 constexpr size_t ZT_LDS_BUDGET = 80 * 1024;  // bytes of LDS per (z,t) tile
+constexpr int FP32_STALL_SWEEPS = 6;  // FP32 sweeps without a new theta minimum: hand over
 
 struct Timer {
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -93,8 +94,9 @@ double normT(const lgf_ctx *c) { return 1.0 / ((double)c->g.nc * (double)c->g.V)
 // Stopping-test parameters for the sweep kernels (enabled == false: the
 // kernel only writes block partials).
 fin_params finp(const lgf_ctx *c, bool enabled, double tol = 0, int max_iter = 0,
-                int increment = 0) {
+                int increment = 0, int stall = 0) {
     fin_params f;
+    f.stall = stall;
     f.normF = normF(c);
     f.normT = normT(c);
     f.tol = tol;
@@ -194,11 +196,11 @@ int read_status(lgf_ctx *c, dev_status &out) {
 // current links are in buffer (n % 2) and `st` holds the final state.
 template <class T>
 int run_phase(lgf_ctx *c, double alpha, double tol, int max_iter, bool accG, int hist_base,
-              dev_status &st) {
+              dev_status &st, int stall = 0) {
     using P = prec<T>;
     HIPCHK(c, launch_status_reset(c->status, hist_base, c->stream));
     HIPCHK(c, launch_div_reduce<T>(c->g, P::links(c, 0), P::field(c, 0), c->partials, c->status,
-                                   finp(c, true, tol, max_iter, 0), c->stream));
+                                   finp(c, true, tol, max_iter, 0, stall), c->stream));
     int rc = read_status(c, st);
     if (rc) return rc;
     const T half_alpha = (T)(0.5 * alpha);
@@ -221,7 +223,8 @@ int run_phase(lgf_ctx *c, double alpha, double tol, int max_iter, bool accG, int
         n_prev = st.n;
         for (int i = 0; i < k; ++i) {
             const int cur = (enq + i) & 1;
-            HIPCHK(c, enqueue_sweep<T>(c, cur, half_alpha, accG, finp(c, true, tol, max_iter, 1)));
+            HIPCHK(c, enqueue_sweep<T>(c, cur, half_alpha, accG,
+                                       finp(c, true, tol, max_iter, 1, stall)));
         }
         enq += k;
         rc = read_status(c, st);
@@ -236,6 +239,7 @@ int status_to_code(int code) {
     case ST_MAXITER: return LGF_NOT_CONVERGED;
     case ST_NONFINITE: return LGF_ERR_NONFINITE;
     case ST_DIVERGING: return LGF_DIVERGING;
+    case ST_STALLED: return LGF_NOT_CONVERGED;
     default: return LGF_OK;
     }
 }
@@ -525,13 +529,15 @@ static int solve(lgf_ctx *c, double *U, double alpha, double tol, int max_iter, 
         HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g, c->stream));
         HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->g.S, c->stream));
         const double tol32 = std::max(tol, c->theta_switch);
-        rc = run_phase<float>(c, alpha, tol32, max_iter, true, 0, st);
+        // the FP32 phase also ends when theta stops reaching new minima (its
+        // rounding floor lies above the hand-over threshold)
+        rc = run_phase<float>(c, alpha, tol32, max_iter, true, 0, st, FP32_STALL_SWEEPS);
         if (rc) return rc;
         n32 = st.n;
         code = st.code;
         // hand-over: U = G U0 G^dagger in FP64 (G reunitarised in FP64)
         HIPCHK(c, launch_switch(c->g, c->G32, U, c->L64[0], c->stream));
-        if (code == ST_CONVERGED || code == ST_MAXITER) {
+        if (code == ST_CONVERGED || code == ST_MAXITER || code == ST_STALLED) {
             rc = run_phase<double>(c, alpha, tol, max_iter - n32, false, n32, st);
             if (rc) return rc;
             n64 = st.n;

@@ -15,10 +15,15 @@ struct dev_status {
     int code;       // 0 running, 1 converged, 4 max_iter, 5 non-finite, 6 diverging
     int rises;      // consecutive iterations with rising theta
     int hist_base;  // history slot of this phase's n = 0
-    int pad;
+    int since_min;  // sweeps since theta last reached a new minimum
 };
 
-enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXITER = 4, ST_NONFINITE = 5, ST_DIVERGING = 6 };
+// ST_STALLED: theta stopped reaching new minima (the FP32 phase of a mixed
+// solve has hit its rounding floor; the solve hands over to FP64).
+enum {
+    ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXITER = 4, ST_NONFINITE = 5, ST_DIVERGING = 6,
+    ST_STALLED = 7
+};
 // Divergence: theta rose DIVERGE_RISES sweeps in a row and exceeds
 // DIVERGE_GROWTH times its smallest value so far (plain steepest descent lets
 // theta rise for a while as F still increases, so rises alone are no test).
@@ -31,6 +36,7 @@ constexpr double DIVERGE_GROWTH = 100.0;
 struct fin_params {
     double normF, normT, tol;
     int max_iter, increment, hist_cap, enabled;
+    int stall;  // > 0: stop with ST_STALLED after this many sweeps without a new minimum
     double *histF, *histT;
 };
 

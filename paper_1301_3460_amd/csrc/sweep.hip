@@ -136,9 +136,13 @@ __device__ __forceinline__ void finalize_state(double A, double B, dev_status *s
         st.code = ST_MAXITER;
     } else {
         st.rises = (st.n > 0 && th > st.theta_prev) ? st.rises + 1 : 0;
+        st.since_min = (st.n == 0 || th < st.theta_min) ? 0 : st.since_min + 1;
         if (st.rises >= DIVERGE_RISES && th > DIVERGE_GROWTH * st.theta_min) {
             st.done = 1;
             st.code = ST_DIVERGING;
+        } else if (fp.stall > 0 && st.since_min >= fp.stall) {
+            st.done = 1;
+            st.code = ST_STALLED;
         }
     }
     st.theta_prev = th;
@@ -310,7 +314,7 @@ __global__ void k_status_reset(dev_status *status, int hist_base) {
     st.code = ST_RUNNING;
     st.rises = 0;
     st.hist_base = hist_base;
-    st.pad = 0;
+    st.since_min = 0;
     *status = st;
 }
 

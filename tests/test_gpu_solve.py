@@ -228,3 +228,16 @@ def test_link_format_rejects_other_sizes(lgf_gpu):
             c.set_link_format(bad)
     r = c.fix(U, ALPHA, 1e-15, 10)
     assert r.status == 0 and r.iterations == 0
+
+
+def test_mixed_fp32_phase_hands_over_when_it_stalls(lgf_gpu):
+    """A hand-over threshold below the FP32 rounding floor: the FP32 phase ends
+    when theta stops reaching new minima and FP64 finishes the solve."""
+    U, _ = inputs.make_config((8, 8, 8, 8), 0.5, 36)
+    ref = oracle.fix(U, ALPHA, 1e-14, 1000)
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, ALPHA, 1e-14, precision="mixed", max_iter=1000, theta_switch=1e-30)
+    assert r.status == 0
+    assert 0 < r.fp32_iterations < 200 and r.iterations > r.fp32_iterations
+    _check_solution(cpu(Ug), U, 1e-14, r.F)
+    assert abs(r.F - ref["F"]) < 1e-12

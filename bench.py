@@ -76,6 +76,10 @@ def main() -> int:
     ap.add_argument("--solves", type=int, default=5, help="repeats per time-to-theta solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=12)
+    ap.add_argument("--lattice", choices=("32^4", "48^3x96"), default="32^4",
+                    help="with --sweeps-only: the lattice whose sweeps are timed and profiled")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 48^3x96 lattice (10.6M sites, beyond the 256 MB cache)")
     ap.add_argument("--sweeps-only", action="store_true",
                     help="only the timed sweeps, the per-kernel timing and one device copy of "
                          "the 32^4 link field (a known-size reference for HBM counters)")
@@ -93,7 +97,13 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     lgf.load()
-    V = int(np.prod(L))
+    Lrun, lat_key = (L, "32^4")
+    if args.lattice != "32^4":
+        if not args.sweeps_only:
+            print("--lattice applies to --sweeps-only runs", file=sys.stderr)
+            return 2
+        Lrun, lat_key = ((48, 48, 48, 96), "48^3x96")
+    V = int(np.prod(Lrun))
     golden = {}
     gpath = os.path.join(ROOT, "tests", "golden", "oracle_324.json")
     if os.path.exists(gpath):
@@ -121,15 +131,15 @@ def main() -> int:
     configs = {}
     for eps in ((EPS_MAIN,) if args.sweeps_only else EPS_ALL):
         t0 = time.time()
-        U, _ = inputs.make_config(L, eps, inputs.CONFIG_SEEDS[("32^4", eps)])
+        U, _ = inputs.make_config(Lrun, eps, inputs.CONFIG_SEEDS[(lat_key, eps)])
         configs[eps] = torch.from_numpy(U).to("cuda")
-        log(f"generated 32^4 eps={eps} in {time.time() - t0:.1f} s")
+        log(f"generated {lat_key} eps={eps} in {time.time() - t0:.1f} s")
         del U
     U0 = configs[EPS_MAIN]
     work = torch.empty_like(U0)
 
-    ctx64 = lgf.Context(L, "fp64")
-    ctx32 = lgf.Context(L, "mixed")
+    ctx64 = lgf.Context(Lrun, "fp64")
+    ctx32 = lgf.Context(Lrun, "mixed")
 
     # ---- sweep throughput (the headline value): K sweeps after W warmup sweeps
     work.copy_(U0)
@@ -298,6 +308,38 @@ def main() -> int:
     log(f"SU(2): {entry}")
     c2.close()
     del U2, w2
+
+    # 48^3 x 96: radix-3 and two-pass transform extents; every working set far
+    # beyond the 256 MB Infinity Cache, so HBM rates are not flattered by it
+    if not args.no_large:
+        L48 = (48, 48, 48, 96)
+        V48 = int(np.prod(L48))
+        t0 = time.time()
+        U48 = torch.from_numpy(
+            inputs.make_config(L48, 0.45, inputs.CONFIG_SEEDS[("48^3x96", 0.45)])[0]).to("cuda")
+        log(f"generated 48^3x96 in {time.time() - t0:.1f} s")
+        w48 = torch.empty_like(U48)
+        c48 = lgf.Context(L48, "fp64")
+        w48.copy_(U48)
+        c48.iterate(w48, ALPHA, 3)
+        w48.copy_(U48)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n48 = 20
+        c48.iterate(w48, ALPHA, n48)
+        torch.cuda.synchronize()
+        ips48 = n48 / (time.perf_counter() - t0)
+        prof48 = c48.profile(U48, ALPHA, 5)
+        variants["48^3x96/fp64"] = {
+            "sweeps_per_s": round(ips48, 2),
+            "per_kernel_ms": {k: round(v, 4) for k, v in prof48.items()},
+            "update_GBps": round(BYTES_PER_SITE["fp64"]["update"] * V48 /
+                                 (prof48["update"] * 1e-3) / 1e9, 1),
+            "sweep_GBps": round(1280 * V48 * ips48 / 1e9, 1)}
+        log(f"48^3x96: {variants['48^3x96/fp64']}")
+        c48.close()
+        del U48, w48
+        torch.cuda.empty_cache()
 
     ctx64.set_acceleration(False)
     work.copy_(U0)

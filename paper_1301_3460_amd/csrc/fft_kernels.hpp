@@ -35,7 +35,7 @@ __device__ __forceinline__ T fa_factor(T base, T pz, T p2max_over_V) {
 // (x, y) plane transform: one plane of one field per block, LDS [y][x+1]
 // ---------------------------------------------------------------------------
 
-constexpr int XY_BLOCK = 64;
+constexpr int XY_BLOCK = 256;
 
 template <class T, int DIR>
 __global__ void __launch_bounds__(XY_BLOCK)
@@ -71,106 +71,77 @@ __global__ void __launch_bounds__(XY_BLOCK)
 }
 
 // ---------------------------------------------------------------------------
-// (z, t) transform of W consecutive xy-sites of one field per block.
-// LDS element (w, z, t) at t*PT + z*W + w, PT = Lz*W + ZT_PAD.
-// MODE 0: forward z,t; scale by p2max/(V p2); inverse t,z.  -1 / +1: one way.
+// One-axis passes for (z, t) planes too large for a register column (an
+// extent above 32): the (z,t) transform becomes three passes over the field,
+// z forward, then t forward / scaling / t inverse, then z inverse.  A block
+// holds W consecutive xy-sites (rows of up to 1 KB) x the whole axis x B
+// slices of the other axis, so every load and store is a coalesced row;
+// the transform of each column runs in LDS (lds_axis_fft, one or two passes).
+// LDS element (w, j, b) at b*N*PW + j*PW + w, PW = W + 1.
+// AX = 2: the z axis (slices along t); AX = 3: the t axis (slices along z).
+// MODE -1 forward, +1 inverse, 0 (t axis only) forward, times p2max/(V p2),
+// inverse.
 // ---------------------------------------------------------------------------
 
-constexpr int ZT_BLOCK = 256;
+constexpr int AXIS_BLOCK = 256;
 constexpr int ZT_PAD = 4;
 
-template <int N, class T, class Base, class Scale>
-__device__ __forceinline__ void t_fwd_scale_inv(vec2_t<T> *lds, int ncols, int stride, Base base,
-                                                Scale scale, const vec2_t<T> *__restrict__ tw) {
-    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
-        const int b0 = base(c);
-        cpx<T> a[N];
-#pragma unroll
-        for (int j = 0; j < N; ++j) a[j] = ld<T>(lds + b0 + j * stride);
-        dft<N, -1>(a, tw);
-#pragma unroll
-        for (int j = 0; j < N; ++j) a[j] = scale(c, j) * a[j];
-        dft<N, +1>(a, tw);
-#pragma unroll
-        for (int j = 0; j < N; ++j) st<T>(lds + b0 + j * stride, a[j]);
-    }
-}
-
-template <class T, int MODE>
-__global__ void __launch_bounds__(ZT_BLOCK)
-    k_fft_zt(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
-             const T *__restrict__ ptab, T p2max_over_V, int W,
-             const dev_status *__restrict__ status) {
+template <class T, int AX, int MODE>
+__global__ void __launch_bounds__(AXIS_BLOCK)
+    k_fft_axis(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
+               const T *__restrict__ ptab, T p2max_over_V, int W, int B,
+               const dev_status *__restrict__ status) {
     if (status->done) return;
     extern __shared__ unsigned char smem_raw[];
     vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
-    const int Lz = g.Lz, Lt = g.Lt;
+    const int Lz = g.Lz, N = AX == 2 ? g.Lz : g.Lt;
     const long Lxy = (long)g.Lx * g.Ly;
-    const int PT = Lz * W + ZT_PAD;
     const long s0 = (long)xcd_block(blockIdx.x, gridDim.x) * W;
     const int Wt = (int)min((long)W, Lxy - s0);
-    vec2_t<T> *F = D + (long)blockIdx.y * g.S;
-    const int nel = W * Lz * Lt;
-    for (int i = threadIdx.x; i < nel; i += ZT_BLOCK) {
-        const int w = i % W, zt = i / W, z = zt % Lz, t = zt / Lz;
+    const int o0 = blockIdx.y * B;  // first slice of the other axis
+    const int PW = W + 1, PB = N * PW;
+    vec2_t<T> *F = D + (long)blockIdx.z * g.S + s0;
+    // (z, t) plane index of element (j, b)
+    auto zt = [=](int j, int b) { return AX == 2 ? (o0 + b) * Lz + j : j * Lz + (o0 + b); };
+    const int nel = W * N * B;
+    for (int i = threadIdx.x; i < nel; i += AXIS_BLOCK) {
+        const int w = i % W, r = i / W, j = r % N, b = r / N;
         vec2_t<T> v;
         v.x = 0;
         v.y = 0;
-        if (w < Wt) v = F[(long)zt * Lxy + s0 + w];
-        lds[t * PT + z * W + w] = v;
+        if (w < Wt) v = F[(long)zt(j, b) * Lxy + w];
+        lds[b * PB + j * PW + w] = v;
     }
     __syncthreads();
-    auto zcol = [W, PT](int c) { return (c / W) * PT + (c % W); };  // c = w + W*t
-    auto tcol = [W](int c) { return c; };                          // c = w + W*z
-    if (MODE <= 0) {
-        lds_axis_fft<-1, T>(Lz, lds, W * Lt, W, zcol, tw);
-        __syncthreads();
-    }
+    auto col = [W, PW, PB](int c) { return (c / W) * PB + (c % W); };  // c = w + W*b
     if (MODE == 0) {
+        lds_axis_fft<-1, T>(N, lds, W * B, PW, col, tw);
+        __syncthreads();
         const T *px = ptab, *py = ptab + g.Lx, *pz = ptab + g.Lx + g.Ly,
                 *pt = ptab + g.Lx + g.Ly + g.Lz;
-        const int Lx = g.Lx, s0i = (int)s0, Lxyi = (int)Lxy;
-        // column c = w + W*z along t: element j is at t position j
-        auto scale = [=](int c, int j) -> T {
-            const int sxy = s0i + (c % W);
-            if (sxy >= Lxyi) return T(0);  // padding column of a ragged tile
-            const int y = sxy / Lx, x = sxy - y * Lx;
-            return fa_factor<T>((px[x] + py[y]) + pz[c / W], pt[j], p2max_over_V);
-        };
-        switch (Lt) {
-#define LGF_TCASE(NN) \
-    case NN: t_fwd_scale_inv<NN, T>(lds, W * Lz, PT, tcol, scale, tw); break;
-            LGF_TCASE(2) LGF_TCASE(3) LGF_TCASE(4) LGF_TCASE(6) LGF_TCASE(8) LGF_TCASE(12)
-            LGF_TCASE(16) LGF_TCASE(24) LGF_TCASE(32)
-#undef LGF_TCASE
-        default: {
-            lds_axis_fft<-1, T>(Lt, lds, W * Lz, PT, tcol, tw);
-            __syncthreads();
-            for (int i = threadIdx.x; i < W * Lz * Lt; i += ZT_BLOCK) {
-                const int c = i % (W * Lz), j = i / (W * Lz);
-                vec2_t<T> *p = lds + j * PT + c;
-                const T f = scale(c, j);
-                vec2_t<T> v = *p;
-                v.x *= f;
-                v.y *= f;
-                *p = v;
+        for (int i = threadIdx.x; i < nel; i += AXIS_BLOCK) {
+            const int w = i % W, r = i / W, j = r % N, b = r / N;
+            const long sxy = s0 + w;
+            T f = 0;  // padding columns of a ragged tile stay zero
+            if (sxy < Lxy) {
+                const int y = (int)(sxy / g.Lx), x = (int)(sxy - (long)y * g.Lx);
+                f = fa_factor<T>((px[x] + py[y]) + pz[o0 + b], pt[j], p2max_over_V);
             }
-            __syncthreads();
-            lds_axis_fft<+1, T>(Lt, lds, W * Lz, PT, tcol, tw);
-        } break;
+            vec2_t<T> *q = lds + b * PB + j * PW + w;
+            vec2_t<T> v = *q;
+            v.x *= f;
+            v.y *= f;
+            *q = v;
         }
         __syncthreads();
+        lds_axis_fft<+1, T>(N, lds, W * B, PW, col, tw);
     } else {
-        lds_axis_fft<MODE, T>(Lt, lds, W * Lz, PT, tcol, tw);
-        __syncthreads();
+        lds_axis_fft<MODE, T>(N, lds, W * B, PW, col, tw);
     }
-    if (MODE >= 0) {
-        lds_axis_fft<+1, T>(Lz, lds, W * Lt, W, zcol, tw);
-        __syncthreads();
-    }
-    for (int i = threadIdx.x; i < nel; i += ZT_BLOCK) {
-        const int w = i % W, zt = i / W, z = zt % Lz, t = zt / Lz;
-        if (w < Wt) F[(long)zt * Lxy + s0 + w] = lds[t * PT + z * W + w];
+    __syncthreads();
+    for (int i = threadIdx.x; i < nel; i += AXIS_BLOCK) {
+        const int w = i % W, r = i / W, j = r % N, b = r / N;
+        if (w < Wt) F[(long)zt(j, b) * Lxy + w] = lds[b * PB + j * PW + w];
     }
 }
 
@@ -385,7 +356,7 @@ template <class T> zt_plan plan_zt(const geom &g, size_t lds_budget) {
     const long Lxy = (long)g.Lx * g.Ly;
     if (g.Lt <= 32 && g.Lz <= 32) {
         auto rc_bytes = [&](int w) {
-            return (size_t)rc_chunk(g.Lt) * ((size_t)g.Lz * w + ZT_PAD) * sizeof(vec2_t<T>);
+            return (size_t)g.Lt * ((size_t)g.Lz * w + ZT_PAD) * sizeof(vec2_t<T>);
         };
         int W = 128 / (int)sizeof(vec2_t<T>);
         while (W > 1 && (W * g.Lz > rc_max_threads<T>() || W > Lxy || rc_bytes(W) > lds_budget))
@@ -397,12 +368,28 @@ template <class T> zt_plan plan_zt(const geom &g, size_t lds_budget) {
             return p;
         }
     }
-    int W = 16;
-    auto bytes = [&](int w) { return (size_t)g.Lt * ((size_t)g.Lz * w + ZT_PAD) * sizeof(vec2_t<T>); };
-    while (W > 1 && ((long)W > Lxy || bytes(W) > lds_budget)) W >>= 1;
+    // one-axis passes: rows of up to 1 KB (W consecutive sites), then as many
+    // slices of the other axis as keep a tile within 64 KB, dividing its extent
+    auto tile = [&](int n, int w, int b) { return (size_t)b * n * (w + 1) * sizeof(vec2_t<T>); };
+    auto width = [&](int n) {
+        int w = 1024 / (int)sizeof(vec2_t<T>);
+        while (w > 1 && (w > Lxy || tile(n, w, 1) > 64 * 1024)) w >>= 1;
+        return w;
+    };
+    auto slices = [&](int n, int w, int other) {
+        int b = 8;
+        while (b > 1 && (other % b != 0 || tile(n, w, b) > 64 * 1024)) b >>= 1;
+        return b;
+    };
     p.rc = false;
-    p.W = W;
-    p.lds = bytes(W);
+    p.Wz = width(g.Lz);
+    p.Wt = width(g.Lt);
+    p.W = p.Wz;
+    p.Bz = slices(g.Lz, p.Wz, g.Lt);
+    p.Bt = slices(g.Lt, p.Wt, g.Lz);
+    p.ldsz = tile(g.Lz, p.Wz, p.Bz);
+    p.ldst = tile(g.Lt, p.Wt, p.Bt);
+    p.lds = std::max(p.ldsz, p.ldst);
     return p;
 }
 
@@ -423,9 +410,11 @@ template <class T> void fft_set_max_lds(const geom &g, const zt_plan &p) {
         }
 #undef LGF_ZTA
     } else {
-        set(reinterpret_cast<const void *>(&k_fft_zt<T, 0>), p.lds);
-        set(reinterpret_cast<const void *>(&k_fft_zt<T, -1>), p.lds);
-        set(reinterpret_cast<const void *>(&k_fft_zt<T, 1>), p.lds);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 2, -1>), p.ldsz);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 2, 1>), p.ldsz);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, 0>), p.ldst);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, -1>), p.ldst);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, 1>), p.ldst);
     }
     if (!xy_use_rc<T>(g)) {
         set(reinterpret_cast<const void *>(&k_fft_xy<T, -1>), fft_xy_lds_bytes<T>(g));
@@ -463,13 +452,36 @@ hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const
 #undef LGF_ZT
         return hipGetLastError();
     }
+    // z forward (mode <= 0), the t pass (forward, scaled round trip or
+    // inverse), z inverse (mode >= 0)
+    const unsigned nf = (unsigned)g.nf;
+    const dim3 gz((unsigned)((Lxy + pl.Wz - 1) / pl.Wz), (unsigned)(g.Lt / pl.Bz), nf);
+    const dim3 gt((unsigned)((Lxy + pl.Wt - 1) / pl.Wt), (unsigned)(g.Lz / pl.Bt), nf);
+    hipError_t e = hipSuccess;
+    auto chk = [&] {
+        if (e == hipSuccess) e = hipGetLastError();
+    };
+    if (mode <= 0) {
+        k_fft_axis<T, 2, -1><<<gz, AXIS_BLOCK, pl.ldsz, st>>>(g, Dp, twp, ptab, p2max_over_V, pl.Wz,
+                                                             pl.Bz, status);
+        chk();
+    }
     if (mode == 0)
-        k_fft_zt<T, 0><<<grid, ZT_BLOCK, pl.lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W, status);
+        k_fft_axis<T, 3, 0><<<gt, AXIS_BLOCK, pl.ldst, st>>>(g, Dp, twp, ptab, p2max_over_V, pl.Wt,
+                                                            pl.Bt, status);
     else if (mode < 0)
-        k_fft_zt<T, -1><<<grid, ZT_BLOCK, pl.lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W, status);
+        k_fft_axis<T, 3, -1><<<gt, AXIS_BLOCK, pl.ldst, st>>>(g, Dp, twp, ptab, p2max_over_V, pl.Wt,
+                                                             pl.Bt, status);
     else
-        k_fft_zt<T, 1><<<grid, ZT_BLOCK, pl.lds, st>>>(g, Dp, twp, ptab, p2max_over_V, W, status);
-    return hipGetLastError();
+        k_fft_axis<T, 3, 1><<<gt, AXIS_BLOCK, pl.ldst, st>>>(g, Dp, twp, ptab, p2max_over_V, pl.Wt,
+                                                            pl.Bt, status);
+    chk();
+    if (mode >= 0) {
+        k_fft_axis<T, 2, 1><<<gz, AXIS_BLOCK, pl.ldsz, st>>>(g, Dp, twp, ptab, p2max_over_V, pl.Wz,
+                                                            pl.Bz, status);
+        chk();
+    }
+    return e;
 }
 
 }  // namespace lgf

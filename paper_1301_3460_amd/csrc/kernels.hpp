@@ -84,9 +84,12 @@ hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw,
 // (z,t) pass plan: register-column kernel (rc) or LDS-tile kernel, tile width
 // W (consecutive xy-sites per block) and dynamic LDS bytes.
 struct zt_plan {
-    bool rc;
-    int W;
-    size_t lds;
+    bool rc;     // register-column kernel (both extents up to 32)
+    int W;       // consecutive xy-sites per block
+    size_t lds;  // LDS bytes (register-column kernel; else the larger pass)
+    // one-axis passes: sites and slices of the other axis per block, LDS bytes
+    int Wz = 1, Wt = 1, Bz = 1, Bt = 1;
+    size_t ldsz = 0, ldst = 0;
 };
 template <class T> zt_plan plan_zt(const geom &g, size_t lds_budget);
 template <class T> size_t fft_xy_lds_bytes(const geom &g);

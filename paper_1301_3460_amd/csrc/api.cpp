@@ -44,7 +44,8 @@ struct lgf_ctx {
     bool accelerate = true;  // false: plain steepest descent (no transform)
     bool exact_exp = false;  // true: g = exp((alpha/2) L Delta) exactly
 
-    // working links, SoA-12: FP64 double buffer; the FP32 pair aliases L64[1]
+    // working links (SoA; 12-real by default, 18-real or SU(2) row 0 by the
+    // context's format): FP64 double buffer; the FP32 pair aliases L64[1]
     double2 *L64[2] = {nullptr, nullptr};
     float2 *L32[2] = {nullptr, nullptr};
     float2 *G32 = nullptr;
@@ -67,7 +68,7 @@ struct lgf_ctx {
     int hist_len = 0;
     // differentiation scratch (allocated on first use)
     double *gaos = nullptr;   // V*9 complex or 4V*9 complex (link exponentials)
-    double2 *Lrot = nullptr;  // SoA-12 FP64 links
+    double2 *Lrot = nullptr;  // 12-real FP64 links (differentiation scratch)
     std::string err;
 };
 

@@ -1,9 +1,11 @@
 // FFT pass kernels and their launchers, templated on the real type.  The
 // translation units fft_f64.hip and fft_f32.hip instantiate them.
 //
-//   k_fft_xy / k_fft_zt        whole tile in LDS (any supported extent)
 //   k_fft_xy_rc / k_fft_zt_rc  one axis held in registers, the other
-//                              exchanged through LDS in chunks (extents <= 32)
+//                              exchanged through LDS (extents <= 32)
+//   k_fft_xy                   a whole (x,y) plane in LDS (larger extents)
+//   k_fft_axis                 one axis of the (z,t) plane per pass, W sites
+//                              x the axis x B slices in LDS (larger extents)
 #pragma once
 #include "common.hpp"
 
@@ -158,7 +160,6 @@ __global__ void __launch_bounds__(AXIS_BLOCK)
 // is chosen on the host so that the tile fits the LDS budget.
 // ---------------------------------------------------------------------------
 
-__host__ __device__ constexpr int rc_chunk(int na) { return na; }
 
 template <int NA, class T, class ColFn>
 __device__ __forceinline__ void exchange_axis(cpx<T> (&a)[NA], int w, int b, int SB, int SW,
@@ -317,7 +318,7 @@ template <class T> inline bool xy_use_rc(const geom &g) { return g.Ly <= 32 && g
 
 template <class T> size_t fft_xy_lds_bytes(const geom &g) {
     if (xy_use_rc<T>(g))
-        return (size_t)rc_chunk(g.Ly) * xy_fields_per_block<T>(g) * (g.Lx + 1) * sizeof(vec2_t<T>);
+        return (size_t)g.Ly * xy_fields_per_block<T>(g) * (g.Lx + 1) * sizeof(vec2_t<T>);
     return (size_t)g.Ly * (g.Lx + 1) * sizeof(vec2_t<T>);
 }
 

@@ -209,13 +209,15 @@ int run_phase(lgf_ctx *c, double alpha, double tol, int max_iter, bool accG, int
     double th_prev = st.theta;
     int n_prev = st.n;
     while (!st.done) {
-        // predict the sweeps still needed from the observed contraction rate
-        int k = 4;
-        if (st.n > n_prev && st.theta > 0 && th_prev > 0) {
+        // sweeps to enqueue before the next status read: a fixed count (tol
+        // <= 0) goes in batches of 64; a solve predicts the sweeps still needed
+        // from the observed contraction rate (clamped before the conversion)
+        int k = tol > 0 ? 4 : 64;
+        if (tol > 0 && st.n > n_prev && st.theta > 0 && th_prev > 0) {
             double rate = std::pow(st.theta / th_prev, 1.0 / (double)(st.n - n_prev));
             rate = std::min(std::max(rate, 1e-3), 0.95);
             const double need = std::log(tol / st.theta) / std::log(rate);
-            k = (int)std::ceil(std::max(need, 1.0));
+            k = (int)std::ceil(std::min(std::max(need, 1.0), 64.0));
         }
         k = std::max(1, std::min(k, 64));
         k = std::min(k, max_iter - enq);

@@ -44,14 +44,23 @@ __global__ void __launch_bounds__(256) k_pack_links(const double2 *__restrict__ 
 template <int NR>
 __global__ void __launch_bounds__(256) k_unpack_links(const double2 *__restrict__ L,
                                                       double2 *__restrict__ U, long V, long S) {
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 4 * V) return;
-    const int mu = (int)(i / V);
-    const long s = i - (long)mu * V;
-    mat3<double> m = load_link<double, NR>(L, S, mu, s);
-    double2 *u = U + i * 9;
+    // The block's 256 links are assembled in LDS and written out as one
+    // contiguous run (consecutive lanes on consecutive 16-byte entries), not
+    // as 144-byte strided pieces per lane.
+    __shared__ double2 buf[256 * 9];
+    const long i0 = (long)blockIdx.x * 256, i = i0 + threadIdx.x;
+    const long n = min(4 * V - i0, 256L);
+    if (i < 4 * V) {
+        const int mu = (int)(i / V);
+        const long s = i - (long)mu * V;
+        const mat3<double> m = load_link<double, NR>(L, S, mu, s);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
+        for (int k = 0; k < 9; ++k)
+            buf[threadIdx.x * 9 + k] = make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
+    }
+    __syncthreads();
+    double2 *u = U + i0 * 9;
+    for (int e = threadIdx.x; e < n * 9; e += 256) u[e] = buf[e];
 }
 
 // anti-hermitian traceless matrix field (AoS 3x3 complex128) <-> 4 Fourier fields

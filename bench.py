@@ -307,6 +307,22 @@ def main() -> int:
     variants["su2/fp64"] = entry
     log(f"SU(2): {entry}")
     c2.close()
+    c2m = lgf.Context(L, "mixed", nc=2)
+    times = []
+    for _ in range(args.solves):
+        w2.copy_(U2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = c2m.fix(w2, ALPHA, TOL, 2000)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    entry = {"solve_ms": round(1e3 * float(np.median(times)), 3), "iterations": res.iterations,
+             "fp32_iterations": res.fp32_iterations, "status": res.status, "F": res.F}
+    if golden_su2:
+        entry["dF_vs_oracle"] = abs(res.F - golden_su2["F"])
+    variants["su2/mixed"] = entry
+    log(f"SU(2) mixed: {entry}")
+    c2m.close()
     del U2, w2
 
     # 48^3 x 96: radix-3 and two-pass transform extents; every working set far

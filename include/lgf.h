@@ -92,9 +92,8 @@ int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream);
  * lgf_create_group(..., 3, ...).  SU(2) contexts take links of shape
  * [4][Lt][Lz][Ly][Lx][2][2] complex128, store row 0 of each link (an SU(2)
  * matrix is [[a, b], [-conj(b), conj(a)]]) and run lgf_fix, lgf_iterate,
- * lgf_theta, lgf_functional (g == NULL), lgf_profile and the step options in
- * LGF_FP64; the other entry points return LGF_ERR_ARG for them, and so does
- * precision LGF_MIXED. */
+ * lgf_theta, lgf_functional (g == NULL), lgf_profile and the step options, in
+ * both precisions; the other entry points return LGF_ERR_ARG for them. */
 int lgf_create_group(lgf_ctx **out, const int L[4], int nc, int precision, void *stream);
 
 /* Free the context's device scratch; NULL is ignored. */

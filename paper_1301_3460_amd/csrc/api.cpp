@@ -321,7 +321,7 @@ int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
     using P = prec<T>;
     const bool accG = std::is_same<T, float>::value;
     HIPCHK(c, launch_pack_links<T>(U, P::links(c, 0), c->g, c->stream));
-    if (accG) HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->g.S, c->stream));
+    if (accG) HIPCHK(c, launch_g_identity(c->G32, c->g, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_div_reduce<T>(c->g, P::links(c, 0), P::field(c, 0), c->partials, c->status,
                                    finp(c, true, 0.0, n + 1, 0), c->stream));
@@ -381,8 +381,6 @@ int lgf_create_group(lgf_ctx **out, const int L[4], int nc, int precision, void 
     if (!out || !L) return fail(nullptr, LGF_ERR_ARG, "null argument");
     *out = nullptr;
     if (nc != 2 && nc != 3) return fail(nullptr, LGF_ERR_ARG, "gauge group must be SU(2) or SU(3)");
-    if (nc == 2 && precision != LGF_FP64)
-        return fail(nullptr, LGF_ERR_ARG, "SU(2) contexts run in LGF_FP64 only");
     if (!shape_ok(L))
         return fail(nullptr, LGF_ERR_ARG,
                     "unsupported lattice extent (allowed: 2 3 4 6 8 12 16 24 32 48 64 96 128)");
@@ -426,7 +424,9 @@ int lgf_create_group(lgf_ctx **out, const int L[4], int nc, int precision, void 
     ok = ok && alloc_links(c);
     ok = ok && alloc((void **)&c->D64[0], (size_t)c->g.nf * S * sizeof(double2));
     ok = ok && alloc((void **)&c->D64[1], (size_t)c->g.nf * S * sizeof(double2));
-    if (precision == LGF_MIXED) ok = ok && alloc((void **)&c->G32, (size_t)6 * S * sizeof(float2));
+    // accumulated transformation (mixed): row 0 and 1 (SU(3)) or row 0 (SU(2))
+    if (precision == LGF_MIXED)
+        ok = ok && alloc((void **)&c->G32, (size_t)(nc == 3 ? 6 : 2) * S * sizeof(float2));
     ok = ok && alloc((void **)&c->tw64, TW_M * sizeof(double2));
     ok = ok && alloc((void **)&c->tw32, TW_M * sizeof(float2));
     const int nt = L[0] + L[1] + L[2] + L[3];
@@ -530,7 +530,7 @@ static int solve(lgf_ctx *c, double *U, double alpha, double tol, int max_iter, 
     if (c->precision == LGF_MIXED) {
         // FP32 phase on a downcast copy; G accumulates the applied transformation
         HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g, c->stream));
-        HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->g.S, c->stream));
+        HIPCHK(c, launch_g_identity(c->G32, c->g, c->stream));
         const double tol32 = std::max(tol, c->theta_switch);
         // the FP32 phase also ends when theta stops reaching new minima (its
         // rounding floor lies above the hand-over threshold)
@@ -595,7 +595,7 @@ int lgf_iterate(lgf_ctx *c, double *U, double alpha, int n_iter, lgf_result *res
     int n32 = 0, n64 = 0, cur64 = 0;
     if (c->precision == LGF_MIXED) {
         HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g, c->stream));
-        HIPCHK(c, launch_g_identity(c->G32, c->g.V, c->g.S, c->stream));
+        HIPCHK(c, launch_g_identity(c->G32, c->g, c->stream));
         rc = run_phase<float>(c, alpha, 0.0, n_iter, true, 0, st);
         if (rc) return rc;
         n32 = st.n;

@@ -110,7 +110,7 @@ hipError_t launch_finalize(const double *partials, int nparts, dev_status *statu
 hipError_t launch_status_reset(dev_status *status, int hist_base, hipStream_t st);
 hipError_t launch_reduce_only(const double *partials, int nparts, double *out2, hipStream_t st);
 
-hipError_t launch_g_identity(void *G32, long V, long S, hipStream_t st);
+hipError_t launch_g_identity(void *G32, const geom &g, hipStream_t st);
 hipError_t launch_switch(const geom &g, const void *G32, const double *U0aos, void *L64,
                          hipStream_t st);
 
@@ -142,7 +142,10 @@ hipError_t launch_div_reduce_su2(const geom &g, const void *L, void *D, double *
                                  dev_status *status, hipStream_t st);
 template <class T>
 hipError_t launch_update_su2(const geom &g, const void *Lin, void *Lout, const void *LD,
-                             void *Dout, T c, bool exact, double *partials, dev_status *status,
+                             void *Dout, void *G, T c, bool exact, double *partials,
+                             dev_status *status, hipStream_t st);
+hipError_t launch_g_identity_su2(void *G32, const geom &g, hipStream_t st);
+hipError_t launch_switch_su2(const geom &g, const void *G32, const double *U0aos, void *L64,
                              hipStream_t st);
 
 }  // namespace lgf

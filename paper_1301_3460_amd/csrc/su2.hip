@@ -10,6 +10,8 @@
 // f0 = Delta01, f1 = Im Delta00 (+ 0i).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "su3.hpp"
@@ -46,7 +48,8 @@ template <class T, bool EXACT> LGF_HD quat<T> gauge_su2(cpx<T> f0, cpx<T> f1, T 
         } else {
             const T w = sqrt(w2);
             T sn;
-            sincos(w, &sn, &cw);
+            if constexpr (std::is_same<T, float>::value) sincosf(w, &sn, &cw);
+            else sincos(w, &sn, &cw);
             sw = sn / w;
         }
         return {mk<T>(cw, sw * al), sw * be};
@@ -135,11 +138,14 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 
 // U_mu(x) <- g(x) U_mu(x) g(x+mu)^dagger, fused with the next Delta (which needs
 // the new U_mu(x-mu) = g(x-mu) U_mu(x-mu) g(x)^dagger) and the F/theta partials.
-template <class T, bool EXACT>
+// ACC_G (the FP32 phase of a mixed solve): also G(x) <- g(x) G(x), G stored as
+// its row 0 like the links.
+template <class T, bool EXACT, bool ACC_G>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_update_su2(geom g, const vec2_t<T> *__restrict__ Lin, vec2_t<T> *__restrict__ Lout,
-                 const vec2_t<T> *__restrict__ LD, vec2_t<T> *__restrict__ Dout, T c,
-                 double *__restrict__ partials, const dev_status *__restrict__ status) {
+                 const vec2_t<T> *__restrict__ LD, vec2_t<T> *__restrict__ Dout,
+                 vec2_t<T> *__restrict__ G, T c, double *__restrict__ partials,
+                 const dev_status *__restrict__ status) {
     if (status->done) return;
     const long s = block_site(g, blockIdx.x, gridDim.x, threadIdx.x);
     double fs = 0, ts = 0;
@@ -164,8 +170,45 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         }
         ts = (double)delta_su2<T>(p, q, Dout, g.S, s);
         fs = (double)tr;
+        if constexpr (ACC_G) {
+            const quat<T> Gn = qmul(g0, quat<T>{ld<T>(G + s), ld<T>(G + g.S + s)});
+            st<T>(G + s, Gn.a);
+            st<T>(G + g.S + s, Gn.b);
+        }
     }
     block_sum2<SITE_BLOCK>(fs, ts, partials, blockIdx.x);
+}
+
+// mixed precision: G = 1, and the hand-over U = G U0 G(x+mu)^dagger in FP64
+// with G normalised in FP64
+__global__ void k_g_identity_su2(float2 *__restrict__ G, long V, long S) {
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    G[s] = make_float2(1.f, 0.f);
+    G[S + s] = make_float2(0.f, 0.f);
+}
+
+__device__ __forceinline__ quat<double> load_G_su2(const float2 *__restrict__ G, long S, long s) {
+    const float2 a = G[s], b = G[S + s];
+    const quat<double> q{mk<double>(a.x, a.y), mk<double>(b.x, b.y)};
+    const double r = rsqrt_nr(norm2(q.a) + norm2(q.b));
+    return {r * q.a, r * q.b};
+}
+
+__global__ void __launch_bounds__(SITE_BLOCK)
+    k_switch_su2(geom g, const float2 *__restrict__ G, const double2 *__restrict__ U0,
+                 double2 *__restrict__ L) {
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V) return;
+    const nbr n = neighbours(g, s);
+    const quat<double> g0 = load_G_su2(G, g.S, s);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const quat<double> gp = load_G_su2(G, g.S, n.p[mu]);
+        const double2 *p = U0 + ((long)mu * g.V + s) * 4;
+        const quat<double> u{mk<double>(p[0].x, p[0].y), mk<double>(p[1].x, p[1].y)};
+        store_q<double>(L, g.S, mu, s, qmul_dag(qmul(g0, u), gp));
+    }
 }
 
 static inline unsigned nblk2(long n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -199,20 +242,39 @@ template hipError_t launch_div_reduce_su2<float>(const geom &, const void *, voi
 
 template <class T>
 hipError_t launch_update_su2(const geom &g, const void *Lin, void *Lout, const void *LD,
-                             void *Dout, T c, bool exact, double *partials, dev_status *status,
-                             hipStream_t st) {
+                             void *Dout, void *G, T c, bool exact, double *partials,
+                             dev_status *status, hipStream_t st) {
     auto go = [&](auto kernel) {
         kernel<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
             g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout),
-            static_cast<const vec2_t<T> *>(LD), static_cast<vec2_t<T> *>(Dout), c, partials,
-            status);
+            static_cast<const vec2_t<T> *>(LD), static_cast<vec2_t<T> *>(Dout),
+            static_cast<vec2_t<T> *>(G), c, partials, status);
     };
-    if (exact) go(k_update_su2<T, true>);
-    else go(k_update_su2<T, false>);
+    // G (the accumulated transformation) exists only in the FP32 phase
+    constexpr bool ACC = std::is_same<T, float>::value;
+    if ((G != nullptr) != ACC) return hipErrorInvalidValue;
+    if (exact) go(k_update_su2<T, true, ACC>);
+    else go(k_update_su2<T, false, ACC>);
     return hipGetLastError();
 }
 template hipError_t launch_update_su2<double>(const geom &, const void *, void *, const void *,
-                                              void *, double, bool, double *, dev_status *,
-                                              hipStream_t);
+                                              void *, void *, double, bool, double *,
+                                              dev_status *, hipStream_t);
+template hipError_t launch_update_su2<float>(const geom &, const void *, void *, const void *,
+                                             void *, void *, float, bool, double *, dev_status *,
+                                             hipStream_t);
+
+hipError_t launch_g_identity_su2(void *G32, const geom &g, hipStream_t st) {
+    k_g_identity_su2<<<nblk2(g.V, 256), 256, 0, st>>>(static_cast<float2 *>(G32), g.V, g.S);
+    return hipGetLastError();
+}
+
+hipError_t launch_switch_su2(const geom &g, const void *G32, const double *U0aos, void *L64,
+                             hipStream_t st) {
+    k_switch_su2<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
+        g, static_cast<const float2 *>(G32), reinterpret_cast<const double2 *>(U0aos),
+        static_cast<double2 *>(L64));
+    return hipGetLastError();
+}
 
 }  // namespace lgf

@@ -748,13 +748,9 @@ hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void 
     if ((G != nullptr) != ACC) return hipErrorInvalidValue;
     auto Gp = static_cast<vec2_t<T> *>(G);
     if (g.nc == 2) {
-        // SU(2) runs in FP64 only (the context refuses mixed precision)
-        if constexpr (ACC) return hipErrorInvalidValue;
-        else {
-            const hipError_t e =
-                launch_update_su2<T>(g, Lin, Lout, LD, Dout, c, exact, partials, status, st);
-            if (e != hipSuccess) return e;
-        }
+        const hipError_t e =
+            launch_update_su2<T>(g, Lin, Lout, LD, Dout, G, c, exact, partials, status, st);
+        if (e != hipSuccess) return e;
     } else if (g.nr == 3) {
         if (exact) go(k_update<T, ACC, true, 3>, Gp);
         else go(k_update<T, ACC, false, 3>, Gp);
@@ -794,13 +790,15 @@ hipError_t launch_reduce_only(const double *partials, int nparts, double *out2, 
     return hipGetLastError();
 }
 
-hipError_t launch_g_identity(void *G32, long V, long S, hipStream_t st) {
-    k_g_identity<<<nblk(V, 256), 256, 0, st>>>(static_cast<float2 *>(G32), V, S);
+hipError_t launch_g_identity(void *G32, const geom &g, hipStream_t st) {
+    if (g.nc == 2) return launch_g_identity_su2(G32, g, st);
+    k_g_identity<<<nblk(g.V, 256), 256, 0, st>>>(static_cast<float2 *>(G32), g.V, g.S);
     return hipGetLastError();
 }
 
 hipError_t launch_switch(const geom &g, const void *G32, const double *U0aos, void *L64,
                          hipStream_t st) {
+    if (g.nc == 2) return launch_switch_su2(g, G32, U0aos, L64, st);
     auto Gp = static_cast<const float2 *>(G32);
     auto U0 = reinterpret_cast<const double2 *>(U0aos);
     auto Lp = static_cast<double2 *>(L64);

@@ -51,23 +51,27 @@ def test_su2_lockstep(lgf_gpu, L, accelerate, exact):
         U = got
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("L,seed_key,tol,exact", [
     ((8, 8, 8, 8), ("su2 8^4", 0.5), 1e-13, False),
     ((8, 8, 8, 8), ("su2 8^4", 0.5), 1e-13, True),
     ((16, 16, 16, 16), ("su2 16^4", 0.5), 1e-15, False),
 ])
-def test_su2_solve_matches_oracle(lgf_gpu, L, seed_key, tol, exact):
+def test_su2_solve_matches_oracle(lgf_gpu, L, seed_key, tol, exact, precision):
     U, _ = inputs.make_config_su2(L, seed_key[1], inputs.CONFIG_SEEDS[seed_key])
     ref = su2.fix(U, ALPHA, tol, 1000, exact_exp=exact)
     assert ref["status"] == 0
     Ug = gpu(U)
-    r = lgf_gpu.fix(Ug, ALPHA, tol, max_iter=1000, exact_exp=exact)
+    r = lgf_gpu.fix(Ug, ALPHA, tol, precision=precision, max_iter=1000, exact_exp=exact)
     assert r.status == 0
     out = cpu(Ug)
     assert su2.theta(out) < tol
     assert abs(r.F - ref["F"]) < 1e-12
     assert abs(su2.F(out) - r.F) < 1e-13
-    assert abs(r.iterations - ref["iterations"]) <= 1
+    if precision == "fp64":
+        assert abs(r.iterations - ref["iterations"]) <= 1
+    else:
+        assert 0 < r.fp32_iterations < r.iterations
     assert abs(su2.plaquette(out) - su2.plaquette(U)) < 1e-12
     mu, md = su2.unitarity(out)
     assert mu < 1e-13 and md < 1e-13
@@ -89,26 +93,38 @@ def test_su2_converged_input_and_errors(lgf_gpu):
     with pytest.raises(lgf_gpu.LgfError):
         lgf_gpu.plaquette(U)
     with pytest.raises(lgf_gpu.LgfError):
-        lgf_gpu.fix(U, ALPHA, 1e-15, precision="mixed")
-    with pytest.raises(lgf_gpu.LgfError):
         lgf_gpu.fix(U, ALPHA, 1e-15, link_format=18)
     with pytest.raises(ValueError):
         lgf_gpu.fix(U.to(torch.complex64), ALPHA, 1e-15)
 
 
-def test_su2_solve_32x4(lgf_gpu):
+def test_su2_mixed_iterate_stays_on_the_orbit(lgf_gpu):
+    """FP32 sweeps with the accumulated transformation applied to the FP64
+    input: exactly on the gauge orbit, close to the FP64 trajectory."""
+    U, _ = inputs.make_config_su2((8, 8, 8, 8), 0.5, 95)
+    Ug = gpu(U)
+    lgf_gpu.iterate(Ug, ALPHA, 6, precision="mixed")
+    out = cpu(Ug)
+    assert abs(su2.plaquette(out) - su2.plaquette(U)) < 1e-13
+    assert su2.unitarity(out)[0] < 1e-14
+    assert np.max(np.abs(out - su2.iterate(U, ALPHA, 6))) < 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_su2_solve_32x4(lgf_gpu, precision):
     with open(GOLDEN) as f:
         ref = json.load(f)["runs"][0]
     U, _ = inputs.make_config_su2((32, 32, 32, 32), ref["eps"], ref["seed"])
     assert su2.plaquette(U) == pytest.approx(ref["plaquette_in"], abs=1e-13)
     Ug = gpu(U)
-    r = lgf_gpu.fix(Ug, ALPHA, 1e-15, max_iter=2000)
+    r = lgf_gpu.fix(Ug, ALPHA, 1e-15, precision=precision, max_iter=2000)
     assert r.status == 0
     out = cpu(Ug)
     del Ug
     assert su2.theta(out) < 1e-15
     assert abs(r.F - ref["F"]) <= 1e-12
-    assert abs(r.iterations - ref["iterations"]) <= 1
+    if precision == "fp64":
+        assert abs(r.iterations - ref["iterations"]) <= 1
     assert abs(su2.plaquette(out) - ref["plaquette_in"]) <= 1e-12
     mu, md = su2.unitarity(out)
     assert mu <= 1e-13 and md <= 1e-13

@@ -246,6 +246,38 @@ def main() -> int:
         log(f"mixed, switch at {sw:g}: {e}")
     ctx32.set_theta_switch(1e-8)
 
+    # FP64 sweeps with the Fourier field held in FP32
+    ctx64.set_field_precision(32)
+    ctx32.set_field_precision(32)
+    work.copy_(U0)
+    ctx64.iterate(work, ALPHA, args.warmup)
+    work.copy_(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx64.iterate(work, ALPHA, args.steps)
+    torch.cuda.synchronize()
+    ipsf = args.steps / (time.perf_counter() - t0)
+    proff = ctx64.profile(U0, ALPHA, 20)
+    e = {"sweeps_per_s": round(ipsf, 1), "per_kernel_ms": {k: round(v, 5) for k, v in proff.items()},
+         "bytes_per_site": 1024}
+    for prec, ctx in (("fp64", ctx64), ("mixed", ctx32)):
+        times = []
+        for _ in range(args.solves):
+            work.copy_(U0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = ctx.fix(work, ALPHA, TOL, 2000)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        e[f"solve_ms_{prec}"] = round(1e3 * float(np.median(times)), 3)
+        e[f"iterations_{prec}"] = res.iterations
+        if golden:
+            e[f"dF_vs_oracle_{prec}"] = abs(res.F - golden[EPS_MAIN]["F"])
+    ctx64.set_field_precision(64)
+    ctx32.set_field_precision(64)
+    variants["field32"] = e
+    log(f"FP32 Fourier field: {e}")
+
     # 18-real working links (all three rows stored) against the 12-real default
     ctx64.set_link_format(18)
     work.copy_(U0)

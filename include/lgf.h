@@ -117,6 +117,17 @@ int lgf_set_acceleration(lgf_ctx *ctx, int on);
  * lgf_fix and lgf_iterate, in both precisions. */
 int lgf_set_exponential(lgf_ctx *ctx, int exact);
 
+/* bits = 64 (default) or 32: the precision in which FP64 sweeps (those of
+ * LGF_FP64 contexts and the FP64 phase of LGF_MIXED) keep the Fourier field,
+ * i.e. Delta and the transformed L Delta between the update and the
+ * transforms.  Links, g(x), the update and the reductions stay FP64, and g is
+ * exactly unitary either way, so an FP32 field only perturbs the step
+ * direction (relative 1e-7): the fixed point and the stopping test are those
+ * of the FP64 method, while the sweep moves 1024 instead of 1280 bytes per
+ * site.  A reading of the method, not the paper's double-precision code.
+ * LGF_ERR_ARG for other values. */
+int lgf_set_field_precision(lgf_ctx *ctx, int bits);
+
 /* Storage of the working links during lgf_fix / lgf_iterate: nreal = 12
  * (default; the paper's "12 real number representation": rows 0 and 1, row 2
  * rebuilt as conj(row0 x row1) on every load) or 18 (all three rows stored, no

@@ -90,6 +90,7 @@ def load(path: str | None = None):
         "lgf_set_acceleration": (c.c_int, [vp, c.c_int]),
         "lgf_set_exponential": (c.c_int, [vp, c.c_int]),
         "lgf_set_link_format": (c.c_int, [vp, c.c_int]),
+        "lgf_set_field_precision": (c.c_int, [vp, c.c_int]),
         "lgf_iterate": (c.c_int, [vp, vp, c.c_double, c.c_int, c.POINTER(_Result)]),
         "lgf_fix": (c.c_int, [vp, vp, c.c_double, c.c_double, c.c_int, c.POINTER(_Result)]),
         "lgf_functional": (c.c_int, [vp, vp, vp, dp]),
@@ -199,6 +200,12 @@ class Context:
         """12 (default, rows 0,1 stored) or 18 (all rows stored) reals per
         working link in fix/iterate."""
         rc = self._lib.lgf_set_link_format(self._h, int(nreal))
+        if rc:
+            self._err(rc)
+
+    def set_field_precision(self, bits: int):
+        """64 (default) or 32: precision of the Fourier field in FP64 sweeps."""
+        rc = self._lib.lgf_set_field_precision(self._h, int(bits))
         if rc:
             self._err(rc)
 
@@ -359,7 +366,7 @@ def _ctx(U, precision="fp64") -> Context:
 
 
 def fix(U, alpha=0.08, theta_tol=1e-15, precision="fp64", max_iter=10000, theta_switch=1e-8,
-        accelerate=True, exact_exp=False, link_format=12):
+        accelerate=True, exact_exp=False, link_format=12, field_bits=64):
     """Gauge-fix U in place; returns a Result (iterations, F, theta, status).
     accelerate=False runs plain (unaccelerated) steepest descent; exact_exp=True
     exponentiates the step exactly; link_format=18 stores all three rows of
@@ -369,16 +376,18 @@ def fix(U, alpha=0.08, theta_tol=1e-15, precision="fp64", max_iter=10000, theta_
         c.set_theta_switch(theta_switch)
     c.set_acceleration(accelerate)
     c.set_exponential(exact_exp)
+    c.set_field_precision(field_bits)
     if c.nc == 3 or link_format != 12:
         c.set_link_format(link_format)
     return c.fix(U, alpha, theta_tol, max_iter)
 
 
 def iterate(U, alpha=0.08, n=1, precision="fp64", accelerate=True, exact_exp=False,
-            link_format=12):
+            link_format=12, field_bits=64):
     c = _ctx(U, precision)
     c.set_acceleration(accelerate)
     c.set_exponential(exact_exp)
+    c.set_field_precision(field_bits)
     if c.nc == 3 or link_format != 12:
         c.set_link_format(link_format)
     return c.iterate(U, alpha, n)

@@ -165,6 +165,28 @@ template <> struct prec<float> {
     static const zt_plan &W(lgf_ctx *c) { return c->zt32; }
 };
 
+// One of the three transform passes of a sweep on the Fourier field D (0: (x,y)
+// forward, 1: (z,t) forward / scaling / inverse, 2: (x,y) inverse), in the
+// field's precision: FP32 for FP32 sweeps and for FP64 sweeps with g.ff32.
+template <class T> bool field32(const lgf_ctx *c) {
+    return std::is_same<T, float>::value || c->g.ff32;
+}
+hipError_t transform_pass(lgf_ctx *c, bool f32, int pass, void *D) {
+    const double k = c->p2max / (double)c->g.V;
+    if (f32) {
+        if (pass == 0) return launch_fft_xy<float>(c->g, D, -1, c->tw32, c->status, c->stream);
+        if (pass == 1)
+            return launch_fft_zt<float>(c->g, D, 0, c->tw32, c->pt32, (float)k, c->zt32,
+                                        c->status, c->stream);
+        return launch_fft_xy<float>(c->g, D, +1, c->tw32, c->status, c->stream);
+    }
+    if (pass == 0) return launch_fft_xy<double>(c->g, D, -1, c->tw64, c->status, c->stream);
+    if (pass == 1)
+        return launch_fft_zt<double>(c->g, D, 0, c->tw64, c->pt64, k, c->zt64, c->status,
+                                     c->stream);
+    return launch_fft_xy<double>(c->g, D, +1, c->tw64, c->status, c->stream);
+}
+
 // One Fourier-accelerated sweep from links/field buffer `cur` into `cur^1`.
 template <class T>
 hipError_t enqueue_sweep(lgf_ctx *c, int cur, T half_alpha, bool accG, const fin_params &fp) {
@@ -172,13 +194,8 @@ hipError_t enqueue_sweep(lgf_ctx *c, int cur, T half_alpha, bool accG, const fin
     hipError_t e;
     void *D = P::field(c, cur);
     if (c->accelerate) {
-        if ((e = launch_fft_xy<T>(c->g, D, -1, P::tw(c), c->status, c->stream)) != hipSuccess)
-            return e;
-        if ((e = launch_fft_zt<T>(c->g, D, 0, P::tw(c), P::pt(c), (T)(c->p2max / (double)c->g.V),
-                                  P::W(c), c->status, c->stream)) != hipSuccess)
-            return e;
-        if ((e = launch_fft_xy<T>(c->g, D, +1, P::tw(c), c->status, c->stream)) != hipSuccess)
-            return e;
+        for (int pass = 0; pass < 3; ++pass)
+            if ((e = transform_pass(c, field32<T>(c), pass, D)) != hipSuccess) return e;
     }
     return launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
                             accG ? c->G32 : nullptr, half_alpha, c->exact_exp, c->partials,
@@ -252,6 +269,7 @@ int status_to_code(int code) {
 geom g12(const lgf_ctx *c) {
     geom g = c->g;
     g.nr = 2;
+    g.ff32 = 0;  // these entry points read the field back in FP64
     return g;
 }
 
@@ -336,12 +354,11 @@ int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
         hipError_t err = hipSuccess;
         auto chk = [&](hipError_t x) { if (err == hipSuccess) err = x; };
         chk(hipEventRecord(e[0], c->stream));
-        chk(launch_fft_xy<T>(c->g, D, -1, P::tw(c), c->status, c->stream));
+        chk(transform_pass(c, field32<T>(c), 0, D));
         chk(hipEventRecord(e[1], c->stream));
-        chk(launch_fft_zt<T>(c->g, D, 0, P::tw(c), P::pt(c), (T)(c->p2max / (double)c->g.V),
-                             P::W(c), c->status, c->stream));
+        chk(transform_pass(c, field32<T>(c), 1, D));
         chk(hipEventRecord(e[2], c->stream));
-        chk(launch_fft_xy<T>(c->g, D, +1, P::tw(c), c->status, c->stream));
+        chk(transform_pass(c, field32<T>(c), 2, D));
         chk(hipEventRecord(e[3], c->stream));
         chk(launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
                              accG ? c->G32 : nullptr, half_alpha, c->exact_exp, c->partials,
@@ -505,6 +522,13 @@ int lgf_set_link_format(lgf_ctx *c, int nreal) {
         (void)alloc_links(c);  // on failure the buffers stay null; check_ctx reports it
         return fail(c, LGF_ERR_OOM, "out of device memory (links)");
     }
+    return LGF_OK;
+}
+
+int lgf_set_field_precision(lgf_ctx *c, int bits) {
+    if (!c) return LGF_ERR_ARG;
+    if (bits != 32 && bits != 64) return fail(c, LGF_ERR_ARG, "field precision must be 32 or 64");
+    c->g.ff32 = bits == 32 ? 1 : 0;
     return LGF_OK;
 }
 
@@ -676,9 +700,9 @@ int lgf_divergence(lgf_ctx *c, const double *U, double *Delta) {
     if (!U || !Delta) return fail(c, LGF_ERR_ARG, "null argument");
     int rc = check_ctx(c);
     if (rc) return rc;
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g, c->stream));
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], g12(c), c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
-    HIPCHK(c, launch_div_reduce<double>(c->g, c->L64[0], c->D64[0], c->partials, c->status,
+    HIPCHK(c, launch_div_reduce<double>(g12(c), c->L64[0], c->D64[0], c->partials, c->status,
                                         finp(c, false), c->stream));
     HIPCHK(c, launch_matrix_from_field(c->D64[0], Delta, c->g.V, c->g.S, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -58,6 +58,8 @@ struct geom {
     // gauge group SU(nc), nc = 3 or 2, and the number of complex Fourier
     // fields carrying Delta (4 for SU(3), 2 for SU(2))
     int nc = 3, nf = 4;
+    // 1: FP64 sweeps keep the Fourier field (Delta, L Delta) in FP32
+    int ff32 = 0;
 };
 
 constexpr int SITE_BLOCK = 256;  // threads per block of the site kernels
@@ -137,10 +139,10 @@ hipError_t launch_theta_grad(const geom &g, const void *L64, const void *D64, co
 template <class T>
 hipError_t launch_pack_su2(const double *Uaos, void *L, const geom &g, hipStream_t st);
 hipError_t launch_unpack_su2(const void *L64, double *Uaos, const geom &g, hipStream_t st);
-template <class T>
+template <class T, class TF>
 hipError_t launch_div_reduce_su2(const geom &g, const void *L, void *D, double *partials,
                                  dev_status *status, hipStream_t st);
-template <class T>
+template <class T, class TF>
 hipError_t launch_update_su2(const geom &g, const void *Lin, void *Lout, const void *LD,
                              void *Dout, void *G, T c, bool exact, double *partials,
                              dev_status *status, hipStream_t st);

@@ -71,11 +71,12 @@ template <class T> LGF_HD void store_q(vec2_t<T> *__restrict__ L, long S, int mu
     st_stream<T>(p + S, u.b);
 }
 
-// Delta fields and Tr[Delta Delta^dagger] from the accumulated (p, q)
-template <class T>
-LGF_HD T delta_su2(cpx<T> p, cpx<T> q, vec2_t<T> *__restrict__ D, long S, long s) {
-    st_stream<T>(D + s, T(2) * q);
-    st_stream<T>(D + S + s, mk<T>(T(2) * p.im, 0));
+// Delta fields (real type TF) and Tr[Delta Delta^dagger] from the
+// accumulated (p, q)
+template <class T, class TF>
+LGF_HD T delta_su2(cpx<T> p, cpx<T> q, vec2_t<TF> *__restrict__ D, long S, long s) {
+    st_stream<TF>(D + s, cvt<TF>(T(2) * q));
+    st_stream<TF>(D + S + s, cvt<TF>(mk<T>(T(2) * p.im, 0)));
     return T(8) * (p.im * p.im + norm2(q));
 }
 
@@ -112,9 +113,9 @@ __global__ void __launch_bounds__(256) k_unpack_su2(const double2 *__restrict__ 
     u[3] = make_double2(a.x, -a.y);
 }
 
-template <class T>
+template <class T, class TF>
 __global__ void __launch_bounds__(SITE_BLOCK)
-    k_div_reduce_su2(geom g, const vec2_t<T> *__restrict__ L, vec2_t<T> *__restrict__ D,
+    k_div_reduce_su2(geom g, const vec2_t<T> *__restrict__ L, vec2_t<TF> *__restrict__ D,
                      double *__restrict__ partials, const dev_status *__restrict__ status) {
     if (status->done) return;
     const long s = block_site(g, blockIdx.x, gridDim.x, threadIdx.x);
@@ -130,7 +131,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
             p = p + (um.a - u.a);
             q = q + (um.b - u.b);
         }
-        ts = (double)delta_su2<T>(p, q, D, g.S, s);
+        ts = (double)delta_su2<T, TF>(p, q, D, g.S, s);
         fs = (double)tr;
     }
     block_sum2<SITE_BLOCK>(fs, ts, partials, blockIdx.x);
@@ -140,10 +141,10 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 // the new U_mu(x-mu) = g(x-mu) U_mu(x-mu) g(x)^dagger) and the F/theta partials.
 // ACC_G (the FP32 phase of a mixed solve): also G(x) <- g(x) G(x), G stored as
 // its row 0 like the links.
-template <class T, bool EXACT, bool ACC_G>
+template <class T, class TF, bool EXACT, bool ACC_G>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_update_su2(geom g, const vec2_t<T> *__restrict__ Lin, vec2_t<T> *__restrict__ Lout,
-                 const vec2_t<T> *__restrict__ LD, vec2_t<T> *__restrict__ Dout,
+                 const vec2_t<TF> *__restrict__ LD, vec2_t<TF> *__restrict__ Dout,
                  vec2_t<T> *__restrict__ G, T c, double *__restrict__ partials,
                  const dev_status *__restrict__ status) {
     if (status->done) return;
@@ -152,7 +153,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
     if (s < g.V) {
         const nbr n = neighbours(g, s);
         auto gauge_at = [&](long x) {
-            return gauge_su2<T, EXACT>(ld<T>(LD + x), ld<T>(LD + g.S + x), c);
+            return gauge_su2<T, EXACT>(cvt<T>(ld<TF>(LD + x)), cvt<T>(ld<TF>(LD + g.S + x)), c);
         };
         const quat<T> g0 = gauge_at(s);
         cpx<T> p = mk<T>(0, 0), q = mk<T>(0, 0);
@@ -168,7 +169,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
             p = p + (umn.a - un.a);
             q = q + (umn.b - un.b);
         }
-        ts = (double)delta_su2<T>(p, q, Dout, g.S, s);
+        ts = (double)delta_su2<T, TF>(p, q, Dout, g.S, s);
         fs = (double)tr;
         if constexpr (ACC_G) {
             const quat<T> Gn = qmul(g0, quat<T>{ld<T>(G + s), ld<T>(G + g.S + s)});
@@ -228,41 +229,46 @@ hipError_t launch_unpack_su2(const void *L64, double *Uaos, const geom &g, hipSt
     return hipGetLastError();
 }
 
-template <class T>
+template <class T, class TF>
 hipError_t launch_div_reduce_su2(const geom &g, const void *L, void *D, double *partials,
                                  dev_status *status, hipStream_t st) {
-    k_div_reduce_su2<T><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
-        g, static_cast<const vec2_t<T> *>(L), static_cast<vec2_t<T> *>(D), partials, status);
+    k_div_reduce_su2<T, TF><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
+        g, static_cast<const vec2_t<T> *>(L), static_cast<vec2_t<TF> *>(D), partials, status);
     return hipGetLastError();
 }
-template hipError_t launch_div_reduce_su2<double>(const geom &, const void *, void *, double *,
-                                                  dev_status *, hipStream_t);
-template hipError_t launch_div_reduce_su2<float>(const geom &, const void *, void *, double *,
-                                                 dev_status *, hipStream_t);
+template hipError_t launch_div_reduce_su2<double, double>(const geom &, const void *, void *,
+                                                          double *, dev_status *, hipStream_t);
+template hipError_t launch_div_reduce_su2<double, float>(const geom &, const void *, void *,
+                                                         double *, dev_status *, hipStream_t);
+template hipError_t launch_div_reduce_su2<float, float>(const geom &, const void *, void *,
+                                                        double *, dev_status *, hipStream_t);
 
-template <class T>
+template <class T, class TF>
 hipError_t launch_update_su2(const geom &g, const void *Lin, void *Lout, const void *LD,
                              void *Dout, void *G, T c, bool exact, double *partials,
                              dev_status *status, hipStream_t st) {
     auto go = [&](auto kernel) {
         kernel<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
             g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout),
-            static_cast<const vec2_t<T> *>(LD), static_cast<vec2_t<T> *>(Dout),
+            static_cast<const vec2_t<TF> *>(LD), static_cast<vec2_t<TF> *>(Dout),
             static_cast<vec2_t<T> *>(G), c, partials, status);
     };
     // G (the accumulated transformation) exists only in the FP32 phase
     constexpr bool ACC = std::is_same<T, float>::value;
     if ((G != nullptr) != ACC) return hipErrorInvalidValue;
-    if (exact) go(k_update_su2<T, true, ACC>);
-    else go(k_update_su2<T, false, ACC>);
+    if (exact) go(k_update_su2<T, TF, true, ACC>);
+    else go(k_update_su2<T, TF, false, ACC>);
     return hipGetLastError();
 }
-template hipError_t launch_update_su2<double>(const geom &, const void *, void *, const void *,
-                                              void *, void *, double, bool, double *,
-                                              dev_status *, hipStream_t);
-template hipError_t launch_update_su2<float>(const geom &, const void *, void *, const void *,
-                                             void *, void *, float, bool, double *, dev_status *,
-                                             hipStream_t);
+template hipError_t launch_update_su2<double, double>(const geom &, const void *, void *,
+                                                      const void *, void *, void *, double, bool,
+                                                      double *, dev_status *, hipStream_t);
+template hipError_t launch_update_su2<double, float>(const geom &, const void *, void *,
+                                                     const void *, void *, void *, double, bool,
+                                                     double *, dev_status *, hipStream_t);
+template hipError_t launch_update_su2<float, float>(const geom &, const void *, void *,
+                                                    const void *, void *, void *, float, bool,
+                                                    double *, dev_status *, hipStream_t);
 
 hipError_t launch_g_identity_su2(void *G32, const geom &g, hipStream_t st) {
     k_g_identity_su2<<<nblk2(g.V, 256), 256, 0, st>>>(static_cast<float2 *>(G32), g.V, g.S);

@@ -48,6 +48,10 @@ template <class T> LGF_HD cpx<T> cmsub(cpx<T> acc, cpx<T> a, cpx<T> b) {
 template <class T> LGF_HD cpx<T> conjg(cpx<T> a) { return {a.re, -a.im}; }
 template <class T> LGF_HD T norm2(cpx<T> a) { return a.re * a.re + a.im * a.im; }
 
+// a complex value in another precision (the Fourier field of FP64 sweeps may
+// be held in FP32)
+template <class U, class T> LGF_HD cpx<U> cvt(cpx<T> a) { return {(U)a.re, (U)a.im}; }
+
 template <class T> LGF_HD cpx<T> ld(const vec2_t<T> *p) {
     vec2_t<T> v = *p;
     return {v.x, v.y};

@@ -163,9 +163,11 @@ __device__ __forceinline__ void finalize_state(double A, double B, dev_status *s
 // divergence and reductions of given links (first sweep of a solve)
 // ---------------------------------------------------------------------------
 
-template <class T, int NR>
+// TF: real type of the Fourier field (T, or float for FP64 sweeps whose field
+// is held in FP32)
+template <class T, class TF, int NR>
 __global__ void __launch_bounds__(SITE_BLOCK)
-    k_div_reduce(geom g, const vec2_t<T> *__restrict__ L, vec2_t<T> *__restrict__ D,
+    k_div_reduce(geom g, const vec2_t<T> *__restrict__ L, vec2_t<TF> *__restrict__ D,
                  double *__restrict__ partials, const dev_status *__restrict__ status) {
     if (status->done) return;
     const long s = block_site(g, blockIdx.x, gridDim.x, threadIdx.x);
@@ -186,10 +188,10 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         cpx<T> f0, f1, f2, f3;
         ts = (double)delta_pack(X, f0, f1, f2, f3);
         fs = (double)tr;
-        st<T>(D + s, f0);
-        st<T>(D + g.S + s, f1);
-        st<T>(D + 2 * g.S + s, f2);
-        st<T>(D + 3 * g.S + s, f3);
+        st<TF>(D + s, cvt<TF>(f0));
+        st<TF>(D + g.S + s, cvt<TF>(f1));
+        st<TF>(D + 2 * g.S + s, cvt<TF>(f2));
+        st<TF>(D + 3 * g.S + s, cvt<TF>(f3));
     }
     block_sum2<SITE_BLOCK>(fs, ts, partials, blockIdx.x);
 }
@@ -198,10 +200,10 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 // fused update + next divergence
 // ---------------------------------------------------------------------------
 
-template <class T, bool ACC_G, bool EXACT, int NR>
+template <class T, class TF, bool ACC_G, bool EXACT, int NR>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_update(geom g, const vec2_t<T> *__restrict__ Lin, vec2_t<T> *__restrict__ Lout,
-             const vec2_t<T> *__restrict__ LD, vec2_t<T> *__restrict__ Dout,
+             const vec2_t<TF> *__restrict__ LD, vec2_t<TF> *__restrict__ Dout,
              vec2_t<T> *__restrict__ G, T c, double *__restrict__ partials,
              const dev_status *__restrict__ status) {
     if (status->done) return;
@@ -222,7 +224,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
             const long sf = (h & 1) ? n.m[mu] : n.p[mu];
             const long sl = (h & 1) ? n.m[mu] : s;
 #pragma unroll
-            for (int f = 0; f < 4; ++f) d.f[f] = ld<T>(LD + (long)f * g.S + sf);
+            for (int f = 0; f < 4; ++f) d.f[f] = cvt<T>(ld<TF>(LD + (long)f * g.S + sf));
             const vec2_t<T> *lp = Lin + (long)mu * 3 * NR * g.S + sl;
 #pragma unroll
             for (int k = 0; k < 3 * NR; ++k) d.u[k] = ld<T>(lp + (long)k * g.S);
@@ -230,7 +232,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         half d[2];
         cpx<T> own[4];
 #pragma unroll
-        for (int f = 0; f < 4; ++f) own[f] = ld<T>(LD + (long)f * g.S + s);
+        for (int f = 0; f < 4; ++f) own[f] = cvt<T>(ld<TF>(LD + (long)f * g.S + s));
         fetch(0, d[0]);
         const mat3<T> g0 = gauge_step<T, EXACT>(own[0], own[1], own[2], own[3], c);
         xacc<T> X;
@@ -259,10 +261,10 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         cpx<T> f0, f1, f2, f3;
         ts = (double)delta_pack(X, f0, f1, f2, f3);
         fs = (double)tr;
-        st_stream<T>(Dout + s, f0);
-        st_stream<T>(Dout + g.S + s, f1);
-        st_stream<T>(Dout + 2 * g.S + s, f2);
-        st_stream<T>(Dout + 3 * g.S + s, f3);
+        st_stream<TF>(Dout + s, cvt<TF>(f0));
+        st_stream<TF>(Dout + g.S + s, cvt<TF>(f1));
+        st_stream<TF>(Dout + 2 * g.S + s, cvt<TF>(f2));
+        st_stream<TF>(Dout + 3 * g.S + s, cvt<TF>(f3));
         if constexpr (ACC_G) {
             // G(x) <- g(x) G(x), rows 0,1 kept (12 reals)
             mat3<T> G0;
@@ -713,18 +715,34 @@ hipError_t launch_unpack_links(const void *L64, double *Uaos, const geom &g, hip
     return hipGetLastError();
 }
 
+// The Fourier field is FP32 for FP32 sweeps and, when g.ff32 is set, for FP64
+// sweeps too; f(tag) runs the body with the field's real type.
+template <class T, class Body> hipError_t with_field_type(const geom &g, Body f) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (g.ff32) return f(float{});
+        return f(double{});
+    } else {
+        return f(float{});
+    }
+}
+
 template <class T>
 hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *partials,
                              dev_status *status, const fin_params &fp, hipStream_t st) {
-    auto Lp = static_cast<const vec2_t<T> *>(L);
-    auto Dp = static_cast<vec2_t<T> *>(D);
-    if (g.nc == 2) {
-        const hipError_t e = launch_div_reduce_su2<T>(g, L, D, partials, status, st);
-        if (e != hipSuccess) return e;
-    } else if (g.nr == 3)
-        k_div_reduce<T, 3><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Lp, Dp, partials, status);
-    else
-        k_div_reduce<T, 2><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Lp, Dp, partials, status);
+    const hipError_t e = with_field_type<T>(g, [&](auto tf) -> hipError_t {
+        using TF = decltype(tf);
+        auto Lp = static_cast<const vec2_t<T> *>(L);
+        auto Dp = static_cast<vec2_t<TF> *>(D);
+        if (g.nc == 2) return launch_div_reduce_su2<T, TF>(g, L, D, partials, status, st);
+        if (g.nr == 3)
+            k_div_reduce<T, TF, 3>
+                <<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Lp, Dp, partials, status);
+        else
+            k_div_reduce<T, TF, 2>
+                <<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Lp, Dp, partials, status);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
     if (fp.enabled) k_finalize<<<1, FIN_BLOCK, 0, st>>>(partials, site_blocks(g.V), status, fp);
     return hipGetLastError();
 }
@@ -737,27 +755,30 @@ template <class T>
 hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void *LD, void *Dout,
                          void *G, T c, bool exact, double *partials, dev_status *status,
                          const fin_params &fp, hipStream_t st) {
-    auto go = [&](auto kernel, vec2_t<T> *Gp) {
-        kernel<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
-            g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout),
-            static_cast<const vec2_t<T> *>(LD), static_cast<vec2_t<T> *>(Dout), Gp, c, partials,
-            status);
-    };
     // G (the accumulated transformation) exists only in the FP32 phase
     constexpr bool ACC = std::is_same<T, float>::value;
     if ((G != nullptr) != ACC) return hipErrorInvalidValue;
-    auto Gp = static_cast<vec2_t<T> *>(G);
-    if (g.nc == 2) {
-        const hipError_t e =
-            launch_update_su2<T>(g, Lin, Lout, LD, Dout, G, c, exact, partials, status, st);
-        if (e != hipSuccess) return e;
-    } else if (g.nr == 3) {
-        if (exact) go(k_update<T, ACC, true, 3>, Gp);
-        else go(k_update<T, ACC, false, 3>, Gp);
-    } else {
-        if (exact) go(k_update<T, ACC, true, 2>, Gp);
-        else go(k_update<T, ACC, false, 2>, Gp);
-    }
+    const hipError_t e = with_field_type<T>(g, [&](auto tf) -> hipError_t {
+        using TF = decltype(tf);
+        if (g.nc == 2)
+            return launch_update_su2<T, TF>(g, Lin, Lout, LD, Dout, G, c, exact, partials, status,
+                                            st);
+        auto go = [&](auto kernel) {
+            kernel<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
+                g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout),
+                static_cast<const vec2_t<TF> *>(LD), static_cast<vec2_t<TF> *>(Dout),
+                static_cast<vec2_t<T> *>(G), c, partials, status);
+        };
+        if (g.nr == 3) {
+            if (exact) go(k_update<T, TF, ACC, true, 3>);
+            else go(k_update<T, TF, ACC, false, 3>);
+        } else {
+            if (exact) go(k_update<T, TF, ACC, true, 2>);
+            else go(k_update<T, TF, ACC, false, 2>);
+        }
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
     if (fp.enabled) k_finalize<<<1, FIN_BLOCK, 0, st>>>(partials, site_blocks(g.V), status, fp);
     return hipGetLastError();
 }

@@ -120,6 +120,24 @@ def test_solve_32x4_link_format_18(lgf_gpu, configs):
     assert mu <= 1e-13 and md <= 1e-13
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_32x4_field32(lgf_gpu, configs, precision):
+    """FP64 sweeps with the Fourier field in FP32: the FP64 method's result."""
+    ref = _golden()[0.45]
+    U = _config(configs, 0.45)
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, 0.08, 1e-15, precision=precision, max_iter=2000, field_bits=32)
+    assert r.status == 0
+    out = Ug.cpu().numpy()
+    del Ug
+    assert oracle.theta(out) < 1e-15
+    assert abs(r.F - ref["F"]) <= 1e-12
+    if precision == "fp64":
+        assert abs(r.iterations - ref["iterations"]) <= 1
+    mu, md = oracle.unitarity(out)
+    assert mu <= 1e-13 and md <= 1e-13
+
+
 def test_lockstep_sweep_32x4_exact_exp(lgf_gpu, configs):
     with open(GOLDEN_EXP) as f:
         ref = json.load(f)["runs"][0]

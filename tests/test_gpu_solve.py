@@ -241,3 +241,37 @@ def test_mixed_fp32_phase_hands_over_when_it_stalls(lgf_gpu):
     assert 0 < r.fp32_iterations < 200 and r.iterations > r.fp32_iterations
     _check_solution(cpu(Ug), U, 1e-14, r.F)
     assert abs(r.F - ref["F"]) < 1e-12
+
+
+# ----------------------------------------------- FP32 Fourier field in FP64 sweeps
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_field32_solve_matches_oracle(lgf_gpu, precision):
+    """The Fourier field in FP32 changes only the step direction (by ~1e-7,
+    relative); the fixed point, the stopping test and the sweep count are
+    those of the FP64 method."""
+    U, _ = inputs.make_config((8, 8, 8, 8), 0.5, inputs.CONFIG_SEEDS[("8^4", 0.5)])
+    ref = oracle.fix(U, ALPHA, 1e-14, 1000)
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, ALPHA, 1e-14, precision=precision, max_iter=1000, field_bits=32)
+    assert r.status == 0
+    _check_solution(cpu(Ug), U, 1e-14, r.F)
+    assert abs(r.F - ref["F"]) < 1e-12
+    if precision == "fp64":
+        assert abs(r.iterations - ref["iterations"]) <= 1
+
+
+def test_field32_sweep_is_a_gauge_transformation(lgf_gpu):
+    U, _ = inputs.make_config((6, 8, 4, 8), 0.5, 37)
+    Ug = gpu(U)
+    lgf_gpu.iterate(Ug, ALPHA, 1, field_bits=32)
+    out = cpu(Ug)
+    ref = oracle.iterate(U, ALPHA, 1)
+    assert np.max(np.abs(out - ref)) < 1e-5
+    assert abs(oracle.plaquette(out) - oracle.plaquette(U)) < 1e-13
+    mu, md = oracle.unitarity(out)
+    assert mu < 1e-13 and md < 1e-13
+    c = lgf_gpu._ctx(Ug)
+    for bad in (16, 0, 128):
+        with pytest.raises(lgf_gpu.LgfError):
+            c.set_field_precision(bad)

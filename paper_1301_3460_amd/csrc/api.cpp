@@ -69,6 +69,8 @@ struct lgf_ctx {
     // differentiation scratch (allocated on first use)
     double *gaos = nullptr;   // V*9 complex or 4V*9 complex (link exponentials)
     double2 *Lrot = nullptr;  // 12-real FP64 links (differentiation scratch)
+    // exactly exponentiated g, rows 0,1 (SU(3) exact step; allocated when enabled)
+    double2 *Gex = nullptr;
     std::string err;
 };
 
@@ -198,7 +200,7 @@ hipError_t enqueue_sweep(lgf_ctx *c, int cur, T half_alpha, bool accG, const fin
             if ((e = transform_pass(c, field32<T>(c), pass, D)) != hipSuccess) return e;
     }
     return launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
-                            accG ? c->G32 : nullptr, half_alpha, c->exact_exp, c->partials,
+                            accG ? c->G32 : nullptr, half_alpha, c->exact_exp, c->Gex, c->partials,
                             c->status, fp, c->stream);
 }
 
@@ -361,7 +363,7 @@ int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
         chk(transform_pass(c, field32<T>(c), 2, D));
         chk(hipEventRecord(e[3], c->stream));
         chk(launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
-                             accG ? c->G32 : nullptr, half_alpha, c->exact_exp, c->partials,
+                             accG ? c->G32 : nullptr, half_alpha, c->exact_exp, c->Gex, c->partials,
                              c->status, finp(c, false), c->stream));
         chk(hipEventRecord(e[4], c->stream));
         chk(launch_finalize(c->partials, c->nparts, c->status, finp(c, true, 0.0, n + 1, 1),
@@ -494,7 +496,7 @@ void lgf_destroy(lgf_ctx *c) {
     else (void)hipDeviceSynchronize();
     void *dev[] = {c->L64[0], c->L64[1], c->D64[0], c->D64[1], c->G32, c->tw64, c->tw32,
                    c->pt64, c->pt32, c->partials, c->status, c->reduce_out, c->histF, c->histT,
-                   c->gaos, c->Lrot};
+                   c->gaos, c->Lrot, c->Gex};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->status_host) (void)hipHostFree(c->status_host);
@@ -534,6 +536,13 @@ int lgf_set_field_precision(lgf_ctx *c, int bits) {
 
 int lgf_set_exponential(lgf_ctx *c, int exact) {
     if (!c) return LGF_ERR_ARG;
+    if (exact && c->g.nc == 3 && !c->Gex) {
+        if (hipSetDevice(c->device) != hipSuccess ||
+            hipMalloc((void **)&c->Gex, (size_t)6 * c->g.S * sizeof(double2)) != hipSuccess) {
+            c->Gex = nullptr;
+            return fail(c, LGF_ERR_OOM, "out of device memory (exact exponential)");
+        }
+    }
     c->exact_exp = exact != 0;
     return LGF_OK;
 }

@@ -74,9 +74,11 @@ template <class T>
 hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *partials,
                              dev_status *status, const fin_params &fp, hipStream_t st);
 
+// exact: g(x) = exp((alpha/2) L Delta) exactly, precomputed into GX (SU(3):
+// 6 complex entries per site, stride S; SU(2) evaluates it in the update).
 template <class T>
 hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void *LD, void *Dout,
-                         void *G, T c, bool exact, double *partials, dev_status *status,
+                         void *G, T c, bool exact, void *GX, double *partials, dev_status *status,
                          const fin_params &fp, hipStream_t st);
 
 // mode: -1 forward only, +1 inverse only (x,y pass: direction)

@@ -269,12 +269,6 @@ LGF_HD mat3<T> gauge_exp_from_entries(cpx<T> f0, cpx<T> f1, cpx<T> f2, cpx<T> f3
     return g;
 }
 
-template <class T, bool EXACT>
-LGF_HD mat3<T> gauge_step(cpx<T> f0, cpx<T> f1, cpx<T> f2, cpx<T> f3, T c) {
-    if constexpr (EXACT) return gauge_exp_from_entries<T>(f0, f1, f2, f3, c);
-    else return gauge_from_entries<T>(f0, f1, f2, f3, c);
-}
-
 // The same from a Fourier field at site s.
 template <class T>
 LGF_HD mat3<T> gauge_from_field(const vec2_t<T> *__restrict__ D, long S, long s, T c) {

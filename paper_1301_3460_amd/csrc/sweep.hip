@@ -200,12 +200,14 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 // fused update + next divergence
 // ---------------------------------------------------------------------------
 
+// EXACT: g was exponentiated exactly beforehand (k_gauge_exp) and is read as
+// rows 0,1 from GX (6 entries per site) instead of being formed from L Delta.
 template <class T, class TF, bool ACC_G, bool EXACT, int NR>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_update(geom g, const vec2_t<T> *__restrict__ Lin, vec2_t<T> *__restrict__ Lout,
-             const vec2_t<TF> *__restrict__ LD, vec2_t<TF> *__restrict__ Dout,
-             vec2_t<T> *__restrict__ G, T c, double *__restrict__ partials,
-             const dev_status *__restrict__ status) {
+             const vec2_t<TF> *__restrict__ LD, const vec2_t<T> *__restrict__ GX,
+             vec2_t<TF> *__restrict__ Dout, vec2_t<T> *__restrict__ G, T c,
+             double *__restrict__ partials, const dev_status *__restrict__ status) {
     if (status->done) return;
     const long s = block_site(g, blockIdx.x, gridDim.x, threadIdx.x);
     double fs = 0, ts = 0;
@@ -213,28 +215,46 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         const nbr n = neighbours(g, s);
         // Eight half-steps h = 2 mu + b: b = 0 transforms the link U_mu(x)
         // with g(x+mu), b = 1 the link U_mu(x-mu) with g(x-mu).  Each needs
-        // 4 field entries and 3*NR link entries; the loads of half-step h+1
-        // are issued before half-step h is computed (software pipelining),
-        // so every wave keeps the next memory round trip in flight.
+        // the 4 field entries of g's site (6 entries of g itself when EXACT)
+        // and 3*NR link entries; the loads of half-step h+1 are issued before
+        // half-step h is computed (software pipelining), so every wave keeps
+        // the next memory round trip in flight.
+        constexpr int NG = EXACT ? 6 : 4;
         struct half {
-            cpx<T> f[4], u[3 * NR];
+            cpx<T> f[NG], u[3 * NR];
+        };
+        auto load_g = [&](long x, cpx<T> (&f)[NG]) {
+#pragma unroll
+            for (int k = 0; k < NG; ++k) {
+                if constexpr (EXACT) f[k] = ld<T>(GX + (long)k * g.S + x);
+                else f[k] = cvt<T>(ld<TF>(LD + (long)k * g.S + x));
+            }
+        };
+        auto make_g = [&](const cpx<T> (&f)[NG]) {
+            mat3<T> m;
+            if constexpr (EXACT) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) m.e[k / 3][k % 3] = f[k];
+                rebuild_row2(m);
+            } else {
+                m = gauge_from_entries<T>(f[0], f[1], f[2], f[3], c);
+            }
+            return m;
         };
         auto fetch = [&](int h, half &d) {
             const int mu = h >> 1;
             const long sf = (h & 1) ? n.m[mu] : n.p[mu];
             const long sl = (h & 1) ? n.m[mu] : s;
-#pragma unroll
-            for (int f = 0; f < 4; ++f) d.f[f] = cvt<T>(ld<TF>(LD + (long)f * g.S + sf));
+            load_g(sf, d.f);
             const vec2_t<T> *lp = Lin + (long)mu * 3 * NR * g.S + sl;
 #pragma unroll
             for (int k = 0; k < 3 * NR; ++k) d.u[k] = ld<T>(lp + (long)k * g.S);
         };
         half d[2];
-        cpx<T> own[4];
-#pragma unroll
-        for (int f = 0; f < 4; ++f) own[f] = cvt<T>(ld<TF>(LD + (long)f * g.S + s));
+        cpx<T> own[NG];
+        load_g(s, own);
         fetch(0, d[0]);
-        const mat3<T> g0 = gauge_step<T, EXACT>(own[0], own[1], own[2], own[3], c);
+        const mat3<T> g0 = make_g(own);
         xacc<T> X;
         xacc_zero(X);
         T tr = 0;
@@ -243,7 +263,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
             if (h < 7) fetch(h + 1, d[(h + 1) & 1]);
             __builtin_amdgcn_sched_barrier(0);
             const half &cur = d[h & 1];
-            const mat3<T> gn = gauge_step<T, EXACT>(cur.f[0], cur.f[1], cur.f[2], cur.f[3], c);
+            const mat3<T> gn = make_g(cur.f);
             mat3<T> u;
 #pragma unroll
             for (int k = 0; k < 3 * NR; ++k) u.e[k / 3][k % 3] = cur.u[k];
@@ -715,6 +735,23 @@ hipError_t launch_unpack_links(const void *L64, double *Uaos, const geom &g, hip
     return hipGetLastError();
 }
 
+// g(x) = exp((alpha/2) L Delta(x)) exactly, once per site, rows 0,1 into GX
+// (the update then reads it at x and its neighbours instead of evaluating the
+// series nine times per site).
+template <class T, class TF>
+__global__ void __launch_bounds__(256)
+    k_gauge_exp(geom g, const vec2_t<TF> *__restrict__ LD, vec2_t<T> *__restrict__ GX, T c,
+                const dev_status *__restrict__ status) {
+    if (status->done) return;
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V) return;
+    const mat3<T> m = gauge_exp_from_entries<T>(
+        cvt<T>(ld<TF>(LD + s)), cvt<T>(ld<TF>(LD + g.S + s)), cvt<T>(ld<TF>(LD + 2 * g.S + s)),
+        cvt<T>(ld<TF>(LD + 3 * g.S + s)), c);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) st<T>(GX + (long)k * g.S + s, m.e[k / 3][k % 3]);
+}
+
 // The Fourier field is FP32 for FP32 sweeps and, when g.ff32 is set, for FP64
 // sweeps too; f(tag) runs the body with the field's real type.
 template <class T, class Body> hipError_t with_field_type(const geom &g, Body f) {
@@ -753,7 +790,7 @@ template hipError_t launch_div_reduce<float>(const geom &, const void *, void *,
 
 template <class T>
 hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void *LD, void *Dout,
-                         void *G, T c, bool exact, double *partials, dev_status *status,
+                         void *G, T c, bool exact, void *GX, double *partials, dev_status *status,
                          const fin_params &fp, hipStream_t st) {
     // G (the accumulated transformation) exists only in the FP32 phase
     constexpr bool ACC = std::is_same<T, float>::value;
@@ -763,11 +800,17 @@ hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void 
         if (g.nc == 2)
             return launch_update_su2<T, TF>(g, Lin, Lout, LD, Dout, G, c, exact, partials, status,
                                             st);
+        if (exact) {
+            if (!GX) return hipErrorInvalidValue;
+            k_gauge_exp<T, TF><<<nblk(g.V, 256), 256, 0, st>>>(
+                g, static_cast<const vec2_t<TF> *>(LD), static_cast<vec2_t<T> *>(GX), c, status);
+        }
         auto go = [&](auto kernel) {
             kernel<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
                 g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout),
-                static_cast<const vec2_t<TF> *>(LD), static_cast<vec2_t<TF> *>(Dout),
-                static_cast<vec2_t<T> *>(G), c, partials, status);
+                static_cast<const vec2_t<TF> *>(LD), static_cast<const vec2_t<T> *>(GX),
+                static_cast<vec2_t<TF> *>(Dout), static_cast<vec2_t<T> *>(G), c, partials,
+                status);
         };
         if (g.nr == 3) {
             if (exact) go(k_update<T, TF, ACC, true, 3>);
@@ -783,10 +826,10 @@ hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void 
     return hipGetLastError();
 }
 template hipError_t launch_update<double>(const geom &, const void *, void *, const void *, void *,
-                                          void *, double, bool, double *, dev_status *,
+                                          void *, double, bool, void *, double *, dev_status *,
                                           const fin_params &, hipStream_t);
 template hipError_t launch_update<float>(const geom &, const void *, void *, const void *, void *,
-                                         void *, float, bool, double *, dev_status *,
+                                         void *, float, bool, void *, double *, dev_status *,
                                          const fin_params &, hipStream_t);
 
 hipError_t launch_reorder_fields(const geom &g, const double2 *in, long si, double2 *out, long so,

@@ -128,3 +128,19 @@ def test_su2_solve_32x4(lgf_gpu, precision):
     assert abs(su2.plaquette(out) - ref["plaquette_in"]) <= 1e-12
     mu, md = su2.unitarity(out)
     assert mu <= 1e-13 and md <= 1e-13
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_su2_field32_solve(lgf_gpu, precision):
+    """FP64 sweeps with the Fourier field in FP32: the FP64 method's result."""
+    U, _ = inputs.make_config_su2((8, 8, 8, 8), 0.5, inputs.CONFIG_SEEDS[("su2 8^4", 0.5)])
+    ref = su2.fix(U, ALPHA, 1e-14, 1000)
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, ALPHA, 1e-14, precision=precision, max_iter=1000, field_bits=32)
+    assert r.status == 0
+    out = cpu(Ug)
+    assert su2.theta(out) < 1e-14
+    assert abs(r.F - ref["F"]) < 1e-12
+    if precision == "fp64":
+        assert abs(r.iterations - ref["iterations"]) <= 1
+    assert abs(su2.plaquette(out) - su2.plaquette(U)) < 1e-12

@@ -399,6 +399,27 @@ def main() -> int:
                                  (prof48["update"] * 1e-3) / 1e9, 1),
             "sweep_GBps": round(1280 * V48 * ips48 / 1e9, 1)}
         log(f"48^3x96: {variants['48^3x96/fp64']}")
+        g48 = None
+        gpath = os.path.join(ROOT, "tests", "golden", "oracle_483x96.json")
+        if os.path.exists(gpath):
+            with open(gpath) as f:
+                g48 = json.load(f)["runs"][0]
+        c48m = lgf.Context(L48, "mixed")
+        for prec, ctx in (("fp64", c48), ("mixed", c48m)):
+            w48.copy_(U48)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = ctx.fix(w48, ALPHA, TOL, 2000)
+            torch.cuda.synchronize()
+            entry = {"ms": round(1e3 * (time.perf_counter() - t0), 3),
+                     "iterations": res.iterations, "fp32_iterations": res.fp32_iterations,
+                     "status": res.status, "F": res.F, "theta": res.theta}
+            if g48:
+                entry["dF_vs_oracle"] = abs(res.F - g48["F"])
+                entry["oracle_iterations"] = g48["iterations"]
+            variants[f"48^3x96/solve_{prec}"] = entry
+            log(f"48^3x96 solve {prec}: {entry}")
+        c48m.close()
         c48.close()
         del U48, w48
         torch.cuda.empty_cache()

@@ -24,6 +24,12 @@ __host__ __device__ constexpr int fft_split(int n) {
     return n == 48 ? 6 : n == 64 ? 8 : n == 96 ? 8 : n == 128 ? 8 : 1;
 }
 
+// complex values one column transform of extent n keeps in registers at a
+// time: the whole column up to 32, else the larger factor of its split
+__host__ __device__ constexpr int fft_reg_span(int n) {
+    return n <= 32 ? n : (fft_split(n) > n / fft_split(n) ? fft_split(n) : n / fft_split(n));
+}
+
 __host__ __device__ constexpr bool fft_supported(int n) {
     return n == 2 || n == 3 || n == 4 || n == 6 || n == 8 || n == 12 || n == 16 || n == 24 ||
            n == 32 || n == 48 || n == 64 || n == 96 || n == 128;
@@ -178,13 +184,18 @@ LGF_HD void lds_axis_fft_n(vec2_t<T> *lds, int ncols, int stride, Base base,
     }
 }
 
-// Runtime-extent dispatch.
-template <int DIR, class T, class Base>
+// Runtime-extent dispatch over the extents whose register span is at most
+// RMAX: a kernel's register allocation is that of its largest case, so a
+// kernel instantiated for spans up to 16 runs at a higher occupancy.
+template <int DIR, class T, int RMAX, class Base>
 LGF_HD void lds_axis_fft(int n, vec2_t<T> *lds, int ncols, int stride, Base base,
                          const vec2_t<T> *__restrict__ tw) {
     switch (n) {
-#define LGF_CASE(NN) \
-    case NN: lds_axis_fft_n<NN, DIR, T>(lds, ncols, stride, base, tw); break;
+#define LGF_CASE(NN)                                                                   \
+    case NN:                                                                           \
+        if constexpr (fft_reg_span(NN) <= RMAX)                                        \
+            lds_axis_fft_n<NN, DIR, T>(lds, ncols, stride, base, tw);                  \
+        break;
         LGF_CASE(2) LGF_CASE(3) LGF_CASE(4) LGF_CASE(6) LGF_CASE(8) LGF_CASE(12) LGF_CASE(16)
         LGF_CASE(24) LGF_CASE(32) LGF_CASE(48) LGF_CASE(64) LGF_CASE(96) LGF_CASE(128)
 #undef LGF_CASE

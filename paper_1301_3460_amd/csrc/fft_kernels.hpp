@@ -39,7 +39,8 @@ __device__ __forceinline__ T fa_factor(T base, T pz, T p2max_over_V) {
 
 constexpr int XY_BLOCK = 256;
 
-template <class T, int DIR>
+// RMAX: largest register span (fft_reg_span) of the extents this instance handles
+template <class T, int DIR, int RMAX>
 __global__ void __launch_bounds__(XY_BLOCK)
     k_fft_xy(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
              const dev_status *__restrict__ status) {
@@ -57,13 +58,13 @@ __global__ void __launch_bounds__(XY_BLOCK)
     auto rows = [P](int c) { return c * P; };
     auto cols = [](int c) { return c; };
     if (DIR < 0) {
-        lds_axis_fft<DIR, T>(Lx, lds, Ly, 1, rows, tw);
+        lds_axis_fft<DIR, T, RMAX>(Lx, lds, Ly, 1, rows, tw);
         __syncthreads();
-        lds_axis_fft<DIR, T>(Ly, lds, Lx, P, cols, tw);
+        lds_axis_fft<DIR, T, RMAX>(Ly, lds, Lx, P, cols, tw);
     } else {
-        lds_axis_fft<DIR, T>(Ly, lds, Lx, P, cols, tw);
+        lds_axis_fft<DIR, T, RMAX>(Ly, lds, Lx, P, cols, tw);
         __syncthreads();
-        lds_axis_fft<DIR, T>(Lx, lds, Ly, 1, rows, tw);
+        lds_axis_fft<DIR, T, RMAX>(Lx, lds, Ly, 1, rows, tw);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < Lxy; i += XY_BLOCK) {
@@ -88,7 +89,7 @@ __global__ void __launch_bounds__(XY_BLOCK)
 constexpr int AXIS_BLOCK = 256;
 constexpr int ZT_PAD = 4;
 
-template <class T, int AX, int MODE>
+template <class T, int AX, int MODE, int RMAX>
 __global__ void __launch_bounds__(AXIS_BLOCK)
     k_fft_axis(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
                const T *__restrict__ ptab, T p2max_over_V, int W, int B,
@@ -117,7 +118,7 @@ __global__ void __launch_bounds__(AXIS_BLOCK)
     __syncthreads();
     auto col = [W, PW, PB](int c) { return (c / W) * PB + (c % W); };  // c = w + W*b
     if (MODE == 0) {
-        lds_axis_fft<-1, T>(N, lds, W * B, PW, col, tw);
+        lds_axis_fft<-1, T, RMAX>(N, lds, W * B, PW, col, tw);
         __syncthreads();
         const T *px = ptab, *py = ptab + g.Lx, *pz = ptab + g.Lx + g.Ly,
                 *pt = ptab + g.Lx + g.Ly + g.Lz;
@@ -136,9 +137,9 @@ __global__ void __launch_bounds__(AXIS_BLOCK)
             *q = v;
         }
         __syncthreads();
-        lds_axis_fft<+1, T>(N, lds, W * B, PW, col, tw);
+        lds_axis_fft<+1, T, RMAX>(N, lds, W * B, PW, col, tw);
     } else {
-        lds_axis_fft<MODE, T>(N, lds, W * B, PW, col, tw);
+        lds_axis_fft<MODE, T, RMAX>(N, lds, W * B, PW, col, tw);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nel; i += AXIS_BLOCK) {
@@ -345,8 +346,13 @@ hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const 
         return hipGetLastError();
     }
     dim3 grid((unsigned)(g.Lz * g.Lt), (unsigned)g.nf);
-    if (dir < 0) k_fft_xy<T, -1><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
-    else k_fft_xy<T, +1><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
+    if (fft_reg_span(g.Lx) <= 16 && fft_reg_span(g.Ly) <= 16) {
+        if (dir < 0) k_fft_xy<T, -1, 16><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
+        else k_fft_xy<T, +1, 16><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
+    } else {
+        if (dir < 0) k_fft_xy<T, -1, 32><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
+        else k_fft_xy<T, +1, 32><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
+    }
     return hipGetLastError();
 }
 
@@ -370,16 +376,20 @@ template <class T> zt_plan plan_zt(const geom &g, size_t lds_budget) {
         }
     }
     // one-axis passes: rows of up to 1 KB (W consecutive sites), then as many
-    // slices of the other axis as keep a tile within 64 KB, dividing its extent
+    // slices of the other axis as keep a tile within AXIS_TILE_BYTES, dividing
+    // its extent.  32 KB tiles let four blocks share a compute unit (the
+    // register limit of these kernels); 64 KB tiles, with wider rows but three
+    // blocks, took 15-25% longer at 48^3 x 96.
+    constexpr size_t AXIS_TILE_BYTES = 32 * 1024;
     auto tile = [&](int n, int w, int b) { return (size_t)b * n * (w + 1) * sizeof(vec2_t<T>); };
     auto width = [&](int n) {
         int w = 1024 / (int)sizeof(vec2_t<T>);
-        while (w > 1 && (w > Lxy || tile(n, w, 1) > 64 * 1024)) w >>= 1;
+        while (w > 1 && (w > Lxy || tile(n, w, 1) > AXIS_TILE_BYTES)) w >>= 1;
         return w;
     };
     auto slices = [&](int n, int w, int other) {
         int b = 8;
-        while (b > 1 && (other % b != 0 || tile(n, w, b) > 64 * 1024)) b >>= 1;
+        while (b > 1 && (other % b != 0 || tile(n, w, b) > AXIS_TILE_BYTES)) b >>= 1;
         return b;
     };
     p.rc = false;
@@ -411,15 +421,23 @@ template <class T> void fft_set_max_lds(const geom &g, const zt_plan &p) {
         }
 #undef LGF_ZTA
     } else {
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 2, -1>), p.ldsz);
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 2, 1>), p.ldsz);
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, 0>), p.ldst);
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, -1>), p.ldst);
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, 1>), p.ldst);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 2, -1, 16>), p.ldsz);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 2, 1, 16>), p.ldsz);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, 0, 16>), p.ldst);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, -1, 16>), p.ldst);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, 1, 16>), p.ldst);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 2, -1, 32>), p.ldsz);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 2, 1, 32>), p.ldsz);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, 0, 32>), p.ldst);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, -1, 32>), p.ldst);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, 1, 32>), p.ldst);
     }
     if (!xy_use_rc<T>(g)) {
-        set(reinterpret_cast<const void *>(&k_fft_xy<T, -1>), fft_xy_lds_bytes<T>(g));
-        set(reinterpret_cast<const void *>(&k_fft_xy<T, 1>), fft_xy_lds_bytes<T>(g));
+        const size_t b = fft_xy_lds_bytes<T>(g);
+        set(reinterpret_cast<const void *>(&k_fft_xy<T, -1, 16>), b);
+        set(reinterpret_cast<const void *>(&k_fft_xy<T, 1, 16>), b);
+        set(reinterpret_cast<const void *>(&k_fft_xy<T, -1, 32>), b);
+        set(reinterpret_cast<const void *>(&k_fft_xy<T, 1, 32>), b);
     }
 }
 
@@ -454,34 +472,34 @@ hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const
         return hipGetLastError();
     }
     // z forward (mode <= 0), the t pass (forward, scaled round trip or
-    // inverse), z inverse (mode >= 0)
+    // inverse), z inverse (mode >= 0); each axis takes the instance for its
+    // extent's register span
     const unsigned nf = (unsigned)g.nf;
     const dim3 gz((unsigned)((Lxy + pl.Wz - 1) / pl.Wz), (unsigned)(g.Lt / pl.Bz), nf);
     const dim3 gt((unsigned)((Lxy + pl.Wt - 1) / pl.Wt), (unsigned)(g.Lz / pl.Bt), nf);
+    const bool zs = fft_reg_span(g.Lz) <= 16, ts = fft_reg_span(g.Lt) <= 16;
     hipError_t e = hipSuccess;
     auto chk = [&] {
         if (e == hipSuccess) e = hipGetLastError();
     };
-    if (mode <= 0) {
-        k_fft_axis<T, 2, -1><<<gz, AXIS_BLOCK, pl.ldsz, st>>>(g, Dp, twp, ptab, p2max_over_V, pl.Wz,
-                                                             pl.Bz, status);
-        chk();
-    }
-    if (mode == 0)
-        k_fft_axis<T, 3, 0><<<gt, AXIS_BLOCK, pl.ldst, st>>>(g, Dp, twp, ptab, p2max_over_V, pl.Wt,
-                                                            pl.Bt, status);
-    else if (mode < 0)
-        k_fft_axis<T, 3, -1><<<gt, AXIS_BLOCK, pl.ldst, st>>>(g, Dp, twp, ptab, p2max_over_V, pl.Wt,
-                                                             pl.Bt, status);
-    else
-        k_fft_axis<T, 3, 1><<<gt, AXIS_BLOCK, pl.ldst, st>>>(g, Dp, twp, ptab, p2max_over_V, pl.Wt,
-                                                            pl.Bt, status);
-    chk();
-    if (mode >= 0) {
-        k_fft_axis<T, 2, 1><<<gz, AXIS_BLOCK, pl.ldsz, st>>>(g, Dp, twp, ptab, p2max_over_V, pl.Wz,
-                                                            pl.Bz, status);
-        chk();
-    }
+#define LGF_AXIS(AXN, MD, GRID, LDSB, WW, BB, SMALL)                                              \
+    do {                                                                                          \
+        if (SMALL)                                                                                \
+            k_fft_axis<T, AXN, MD, 16><<<GRID, AXIS_BLOCK, LDSB, st>>>(g, Dp, twp, ptab,          \
+                                                                      p2max_over_V, WW, BB,       \
+                                                                      status);                    \
+        else                                                                                      \
+            k_fft_axis<T, AXN, MD, 32><<<GRID, AXIS_BLOCK, LDSB, st>>>(g, Dp, twp, ptab,          \
+                                                                      p2max_over_V, WW, BB,       \
+                                                                      status);                    \
+        chk();                                                                                    \
+    } while (0)
+    if (mode <= 0) LGF_AXIS(2, -1, gz, pl.ldsz, pl.Wz, pl.Bz, zs);
+    if (mode == 0) LGF_AXIS(3, 0, gt, pl.ldst, pl.Wt, pl.Bt, ts);
+    else if (mode < 0) LGF_AXIS(3, -1, gt, pl.ldst, pl.Wt, pl.Bt, ts);
+    else LGF_AXIS(3, 1, gt, pl.ldst, pl.Wt, pl.Bt, ts);
+    if (mode >= 0) LGF_AXIS(2, 1, gz, pl.ldsz, pl.Wz, pl.Bz, zs);
+#undef LGF_AXIS
     return e;
 }
 

@@ -19,6 +19,8 @@ SHAPES = [
     (4, 4, 4, 4), (6, 6, 6, 6), (8, 8, 8, 8), (4, 6, 8, 12), (2, 3, 4, 6), (3, 4, 2, 4),
     (12, 12, 12, 12), (48, 4, 4, 6), (4, 48, 6, 4), (4, 4, 48, 8), (4, 6, 4, 96),
     (8, 4, 64, 4), (4, 2, 4, 128), (16, 16, 16, 16),
+    # extents of 24 or 32 beside one above 32 (the wider-register FFT instances)
+    (32, 48, 2, 2), (2, 2, 32, 64), (2, 4, 96, 24),
 ]
 
 

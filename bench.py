@@ -387,7 +387,7 @@ def main() -> int:
         w48.copy_(U48)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        n48 = 20
+        n48 = 100
         c48.iterate(w48, ALPHA, n48)
         torch.cuda.synchronize()
         ips48 = n48 / (time.perf_counter() - t0)

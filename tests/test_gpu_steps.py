@@ -21,6 +21,8 @@ SHAPES = [
     (8, 4, 64, 4), (4, 2, 4, 128), (16, 16, 16, 16),
     # extents of 24 or 32 beside one above 32 (the wider-register FFT instances)
     (32, 48, 2, 2), (2, 2, 32, 64), (2, 4, 96, 24),
+    # 32-wide x rows with even and odd Ly
+    (32, 6, 4, 2), (32, 24, 2, 2), (32, 2, 3, 4), (32, 3, 2, 4),
 ]
 
 

@@ -184,6 +184,105 @@ LGF_HD void lds_axis_fft_n(vec2_t<T> *lds, int ncols, int stride, Base base,
     }
 }
 
+// Column transform forward, times scale(prep(c), position), inverse, in place.
+// Extents up to 32 take one register pass per column.  Two-pass extents take
+// the forward pass 1, then per (column, k1) the forward N2-point DFT, the
+// scaling and the inverse N2-point DFT with its twiddles in registers, then
+// the inverse pass 1: two LDS round trips and two barriers fewer than a
+// forward transform, a scaling pass and an inverse transform, with the same
+// arithmetic in the same order.  Must be called by every thread of the block.
+template <int N, class T, class Base, class Prep, class Scale>
+LGF_HD void lds_axis_fsi_n(vec2_t<T> *lds, int ncols, int stride, Base base, Prep prep,
+                           Scale scale, const vec2_t<T> *__restrict__ tw) {
+    const int nthr = blockDim.x;
+    if constexpr (N <= 32) {
+        for (int c = threadIdx.x; c < ncols; c += nthr) {
+            const int b0 = base(c);
+            const auto info = prep(c);
+            cpx<T> a[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) a[j] = ld<T>(lds + b0 + j * stride);
+            dft<N, -1>(a, tw);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const T f = scale(info, k);
+                a[k].re *= f;
+                a[k].im *= f;
+            }
+            dft<N, +1>(a, tw);
+#pragma unroll
+            for (int j = 0; j < N; ++j) st<T>(lds + b0 + j * stride, a[j]);
+        }
+    } else {
+        constexpr int N1 = fft_split(N), N2 = N / N1;
+        static_assert(N1 * N2 == N && N1 > 1, "unsupported extent");
+        // forward pass 1: for each n2, DFT_N1 over n1 (stride N2), times W_N^(n2 k1)
+        for (int w = threadIdx.x; w < ncols * N2; w += nthr) {
+            const int c = w / N2, n2 = w - c * N2;
+            const int b0 = base(c) + n2 * stride;
+            cpx<T> a[N1];
+#pragma unroll
+            for (int j = 0; j < N1; ++j) a[j] = ld<T>(lds + b0 + j * N2 * stride);
+            dft<N1, -1>(a, tw);
+#pragma unroll
+            for (int k1 = 1; k1 < N1; ++k1) a[k1] = cmul(a[k1], twiddle<N, -1, T>(tw, n2 * k1));
+#pragma unroll
+            for (int j = 0; j < N1; ++j) st<T>(lds + b0 + j * N2 * stride, a[j]);
+        }
+        __syncthreads();
+        // per k1: forward DFT_N2 (position k1 N2 + k2), scaling, inverse DFT_N2,
+        // times W_N^(-n2 k1)
+        for (int w = threadIdx.x; w < ncols * N1; w += nthr) {
+            const int c = w / N1, k1 = w - c * N1;
+            const int b0 = base(c) + k1 * N2 * stride;
+            const auto info = prep(c);
+            cpx<T> a[N2];
+#pragma unroll
+            for (int j = 0; j < N2; ++j) a[j] = ld<T>(lds + b0 + j * stride);
+            dft<N2, -1>(a, tw);
+#pragma unroll
+            for (int k2 = 0; k2 < N2; ++k2) {
+                const T f = scale(info, k1 * N2 + k2);
+                a[k2].re *= f;
+                a[k2].im *= f;
+            }
+            dft<N2, +1>(a, tw);
+#pragma unroll
+            for (int n2 = 1; n2 < N2; ++n2) a[n2] = cmul(a[n2], twiddle<N, +1, T>(tw, n2 * k1));
+#pragma unroll
+            for (int j = 0; j < N2; ++j) st<T>(lds + b0 + j * stride, a[j]);
+        }
+        __syncthreads();
+        // inverse pass 1: for each n2, inverse DFT_N1 over k1 (stride N2)
+        for (int w = threadIdx.x; w < ncols * N2; w += nthr) {
+            const int c = w / N2, n2 = w - c * N2;
+            const int b0 = base(c) + n2 * stride;
+            cpx<T> a[N1];
+#pragma unroll
+            for (int j = 0; j < N1; ++j) a[j] = ld<T>(lds + b0 + j * N2 * stride);
+            dft<N1, +1>(a, tw);
+#pragma unroll
+            for (int j = 0; j < N1; ++j) st<T>(lds + b0 + j * N2 * stride, a[j]);
+        }
+    }
+}
+
+template <class T, int RMAX, class Base, class Prep, class Scale>
+LGF_HD void lds_axis_fsi(int n, vec2_t<T> *lds, int ncols, int stride, Base base, Prep prep,
+                         Scale scale, const vec2_t<T> *__restrict__ tw) {
+    switch (n) {
+#define LGF_CASE(NN)                                                                   \
+    case NN:                                                                           \
+        if constexpr (fft_reg_span(NN) <= RMAX)                                        \
+            lds_axis_fsi_n<NN, T>(lds, ncols, stride, base, prep, scale, tw);          \
+        break;
+        LGF_CASE(2) LGF_CASE(3) LGF_CASE(4) LGF_CASE(6) LGF_CASE(8) LGF_CASE(12) LGF_CASE(16)
+        LGF_CASE(24) LGF_CASE(32) LGF_CASE(48) LGF_CASE(64) LGF_CASE(96) LGF_CASE(128)
+#undef LGF_CASE
+    default: break;
+    }
+}
+
 // Runtime-extent dispatch over the extents whose register span is at most
 // RMAX: a kernel's register allocation is that of its largest case, so a
 // kernel instantiated for spans up to 16 runs at a higher occupancy.

@@ -89,8 +89,11 @@ __global__ void __launch_bounds__(XY_BLOCK)
 constexpr int AXIS_BLOCK = 256;
 constexpr int ZT_PAD = 4;
 
+// Register budgets: 128 VGPRs for spans up to 16 (four waves per SIMD, the
+// occupancy the 32 KB tiles allow; the fused scaled round trip would take
+// 129), 256 for the wider spans (without the hint it spills to AGPRs).
 template <class T, int AX, int MODE, int RMAX>
-__global__ void __launch_bounds__(AXIS_BLOCK)
+__global__ void __launch_bounds__(AXIS_BLOCK) __attribute__((amdgpu_waves_per_eu(RMAX <= 16 ? 4 : 2)))
     k_fft_axis(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
                const T *__restrict__ ptab, T p2max_over_V, int W, int B,
                const dev_status *__restrict__ status) {
@@ -118,26 +121,19 @@ __global__ void __launch_bounds__(AXIS_BLOCK)
     __syncthreads();
     auto col = [W, PW, PB](int c) { return (c / W) * PB + (c % W); };  // c = w + W*b
     if (MODE == 0) {
-        lds_axis_fft<-1, T, RMAX>(N, lds, W * B, PW, col, tw);
-        __syncthreads();
         const T *px = ptab, *py = ptab + g.Lx, *pz = ptab + g.Lx + g.Ly,
                 *pt = ptab + g.Lx + g.Ly + g.Lz;
-        for (int i = threadIdx.x; i < nel; i += AXIS_BLOCK) {
-            const int w = i % W, r = i / W, j = r % N, b = r / N;
+        // per column c = w + W*b: its p2 without the t term, or -1 for a
+        // padding column of a ragged tile (factor 0)
+        auto prep = [=](int c) -> T {
+            const int w = c % W, b = c / W;
             const long sxy = s0 + w;
-            T f = 0;  // padding columns of a ragged tile stay zero
-            if (sxy < Lxy) {
-                const int y = (int)(sxy / g.Lx), x = (int)(sxy - (long)y * g.Lx);
-                f = fa_factor<T>((px[x] + py[y]) + pz[o0 + b], pt[j], p2max_over_V);
-            }
-            vec2_t<T> *q = lds + b * PB + j * PW + w;
-            vec2_t<T> v = *q;
-            v.x *= f;
-            v.y *= f;
-            *q = v;
-        }
-        __syncthreads();
-        lds_axis_fft<+1, T, RMAX>(N, lds, W * B, PW, col, tw);
+            if (sxy >= Lxy) return T(-1);
+            const int y = (int)(sxy / g.Lx), x = (int)(sxy - (long)y * g.Lx);
+            return (px[x] + py[y]) + pz[o0 + b];
+        };
+        auto scale = [=](T base, int j) -> T { return fa_factor<T>(base, pt[j], p2max_over_V); };
+        lds_axis_fsi<T, RMAX>(N, lds, W * B, PW, col, prep, scale, tw);
     } else {
         lds_axis_fft<MODE, T, RMAX>(N, lds, W * B, PW, col, tw);
     }

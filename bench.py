@@ -29,10 +29,12 @@ EPS_MAIN = 0.45
 BYTES_UPDATE_18 = 4 * 144 * 2 + 128  # update with 18-real links: R+W 4 x 144 B, R+W 64 B
 BYTES_UPDATE_SU2 = 4 * 32 * 2 + 32 * 2  # SU(2) update: R+W 4 links x 32 B, R+W 2 fields
 SD_TOL = 1e-10  # plain steepest descent needs thousands of sweeps at 32^4
-# algorithmic bytes per site of each sweep kernel (FP64 / FP32 with G)
+# algorithmic bytes per site of each sweep kernel (FP64; FP32 sweeps of a
+# mixed solve, whose "update" is G <- g G (R field 32, R+W G 96) followed by
+# the update from the input copy U0 (R U0 192, R G 48, W field 32))
 BYTES_PER_SITE = {
     "fp64": {"fft_xy_fwd": 128, "fft_zt": 128, "fft_xy_inv": 128, "update": 896, "finalize": 0},
-    "fp32": {"fft_xy_fwd": 64, "fft_zt": 64, "fft_xy_inv": 64, "update": 448 + 96, "finalize": 0},
+    "fp32": {"fft_xy_fwd": 64, "fft_zt": 64, "fft_xy_inv": 64, "update": 128 + 272, "finalize": 0},
 }
 
 

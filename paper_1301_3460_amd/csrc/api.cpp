@@ -167,6 +167,27 @@ template <> struct prec<float> {
     static const zt_plan &W(lgf_ctx *c) { return c->zt32; }
 };
 
+// The accumulated transformation of the FP32 sweeps after n of them.  SU(3)
+// alternates between G32 and the second FP32 link buffer (free there: the
+// FP32 sweeps keep the constant copy U0 in L32[0] and form G U0 G^dagger);
+// SU(2) updates G32 in place.
+float2 *acc_G(lgf_ctx *c, int n) { return (c->g.nc == 3 && (n & 1)) ? c->L32[1] : c->G32; }
+
+// Arguments of launch_update for the sweep from buffer `cur` into `cur^1`.
+template <class T>
+hipError_t sweep_update(lgf_ctx *c, int cur, void *D, T half_alpha, const fin_params &fp) {
+    using P = prec<T>;
+    if constexpr (std::is_same<T, float>::value) {
+        if (c->g.nc == 3)
+            return launch_update<T>(c->g, c->L32[0], nullptr, D, P::field(c, cur ^ 1),
+                                    acc_G(c, cur), half_alpha, c->exact_exp, acc_G(c, cur ^ 1),
+                                    c->partials, c->status, fp, c->stream);
+    }
+    return launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
+                            std::is_same<T, float>::value ? c->G32 : nullptr, half_alpha,
+                            c->exact_exp, c->Gex, c->partials, c->status, fp, c->stream);
+}
+
 // One of the three transform passes of a sweep on the Fourier field D (0: (x,y)
 // forward, 1: (z,t) forward / scaling / inverse, 2: (x,y) inverse), in the
 // field's precision: FP32 for FP32 sweeps and for FP64 sweeps with g.ff32.
@@ -191,7 +212,7 @@ hipError_t transform_pass(lgf_ctx *c, bool f32, int pass, void *D) {
 
 // One Fourier-accelerated sweep from links/field buffer `cur` into `cur^1`.
 template <class T>
-hipError_t enqueue_sweep(lgf_ctx *c, int cur, T half_alpha, bool accG, const fin_params &fp) {
+hipError_t enqueue_sweep(lgf_ctx *c, int cur, T half_alpha, const fin_params &fp) {
     using P = prec<T>;
     hipError_t e;
     void *D = P::field(c, cur);
@@ -199,9 +220,7 @@ hipError_t enqueue_sweep(lgf_ctx *c, int cur, T half_alpha, bool accG, const fin
         for (int pass = 0; pass < 3; ++pass)
             if ((e = transform_pass(c, field32<T>(c), pass, D)) != hipSuccess) return e;
     }
-    return launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
-                            accG ? c->G32 : nullptr, half_alpha, c->exact_exp, c->Gex, c->partials,
-                            c->status, fp, c->stream);
+    return sweep_update<T>(c, cur, D, half_alpha, fp);
 }
 
 int read_status(lgf_ctx *c, dev_status &out) {
@@ -213,10 +232,11 @@ int read_status(lgf_ctx *c, dev_status &out) {
 }
 
 // Runs one precision phase on the working links in buffer 0.  On return the
-// current links are in buffer (n % 2) and `st` holds the final state.
+// current links (FP64) or accumulated transformation (FP32, acc_G) are those
+// after n = st.n sweeps and `st` holds the final state.
 template <class T>
-int run_phase(lgf_ctx *c, double alpha, double tol, int max_iter, bool accG, int hist_base,
-              dev_status &st, int stall = 0) {
+int run_phase(lgf_ctx *c, double alpha, double tol, int max_iter, int hist_base, dev_status &st,
+              int stall = 0) {
     using P = prec<T>;
     HIPCHK(c, launch_status_reset(c->status, hist_base, c->stream));
     HIPCHK(c, launch_div_reduce<T>(c->g, P::links(c, 0), P::field(c, 0), c->partials, c->status,
@@ -245,8 +265,7 @@ int run_phase(lgf_ctx *c, double alpha, double tol, int max_iter, bool accG, int
         n_prev = st.n;
         for (int i = 0; i < k; ++i) {
             const int cur = (enq + i) & 1;
-            HIPCHK(c, enqueue_sweep<T>(c, cur, half_alpha, accG,
-                                       finp(c, true, tol, max_iter, 1, stall)));
+            HIPCHK(c, enqueue_sweep<T>(c, cur, half_alpha, finp(c, true, tol, max_iter, 1, stall)));
         }
         enq += k;
         rc = read_status(c, st);
@@ -362,9 +381,7 @@ int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
         chk(hipEventRecord(e[2], c->stream));
         chk(transform_pass(c, field32<T>(c), 2, D));
         chk(hipEventRecord(e[3], c->stream));
-        chk(launch_update<T>(c->g, P::links(c, cur), P::links(c, cur ^ 1), D, P::field(c, cur ^ 1),
-                             accG ? c->G32 : nullptr, half_alpha, c->exact_exp, c->Gex, c->partials,
-                             c->status, finp(c, false), c->stream));
+        chk(sweep_update<T>(c, cur, D, half_alpha, finp(c, false)));
         chk(hipEventRecord(e[4], c->stream));
         chk(launch_finalize(c->partials, c->nparts, c->status, finp(c, true, 0.0, n + 1, 1),
                             c->stream));
@@ -567,14 +584,14 @@ static int solve(lgf_ctx *c, double *U, double alpha, double tol, int max_iter, 
         const double tol32 = std::max(tol, c->theta_switch);
         // the FP32 phase also ends when theta stops reaching new minima (its
         // rounding floor lies above the hand-over threshold)
-        rc = run_phase<float>(c, alpha, tol32, max_iter, true, 0, st, FP32_STALL_SWEEPS);
+        rc = run_phase<float>(c, alpha, tol32, max_iter, 0, st, FP32_STALL_SWEEPS);
         if (rc) return rc;
         n32 = st.n;
         code = st.code;
         // hand-over: U = G U0 G^dagger in FP64 (G reunitarised in FP64)
-        HIPCHK(c, launch_switch(c->g, c->G32, U, c->L64[0], c->stream));
+        HIPCHK(c, launch_switch(c->g, acc_G(c, n32), U, c->L64[0], c->stream));
         if (code == ST_CONVERGED || code == ST_MAXITER || code == ST_STALLED) {
-            rc = run_phase<double>(c, alpha, tol, max_iter - n32, false, n32, st);
+            rc = run_phase<double>(c, alpha, tol, max_iter - n32, n32, st);
             if (rc) return rc;
             n64 = st.n;
             code = st.code;
@@ -582,7 +599,7 @@ static int solve(lgf_ctx *c, double *U, double alpha, double tol, int max_iter, 
         }
     } else {
         HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g, c->stream));
-        rc = run_phase<double>(c, alpha, tol, max_iter, false, 0, st);
+        rc = run_phase<double>(c, alpha, tol, max_iter, 0, st);
         if (rc) return rc;
         n64 = st.n;
         code = st.code;
@@ -629,13 +646,13 @@ int lgf_iterate(lgf_ctx *c, double *U, double alpha, int n_iter, lgf_result *res
     if (c->precision == LGF_MIXED) {
         HIPCHK(c, launch_pack_links<float>(U, c->L32[0], c->g, c->stream));
         HIPCHK(c, launch_g_identity(c->G32, c->g, c->stream));
-        rc = run_phase<float>(c, alpha, 0.0, n_iter, true, 0, st);
+        rc = run_phase<float>(c, alpha, 0.0, n_iter, 0, st);
         if (rc) return rc;
         n32 = st.n;
-        HIPCHK(c, launch_switch(c->g, c->G32, U, c->L64[0], c->stream));
+        HIPCHK(c, launch_switch(c->g, acc_G(c, n32), U, c->L64[0], c->stream));
     } else {
         HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g, c->stream));
-        rc = run_phase<double>(c, alpha, 0.0, n_iter, false, 0, st);
+        rc = run_phase<double>(c, alpha, 0.0, n_iter, 0, st);
         if (rc) return rc;
         n64 = st.n;
         cur64 = n64 & 1;

@@ -76,6 +76,12 @@ hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *part
 
 // exact: g(x) = exp((alpha/2) L Delta) exactly, precomputed into GX (SU(3):
 // 6 complex entries per site, stride S; SU(2) evaluates it in the update).
+// T = float (the FP32 sweeps of a mixed solve): G is the accumulated
+// transformation.  SU(3): Lin holds the constant FP32 copy U0 of the input
+// links, G the transformation before the sweep and GX receives it after
+// (g(x) G(x), rows 0,1); the new links G U0 G^dagger are formed in the update
+// and not stored (Lout unused).  SU(2): links go from Lin to Lout and G is
+// updated in place.
 template <class T>
 hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void *LD, void *Dout,
                          void *G, T c, bool exact, void *GX, double *partials, dev_status *status,

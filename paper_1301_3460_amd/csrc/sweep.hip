@@ -200,14 +200,18 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 // fused update + next divergence
 // ---------------------------------------------------------------------------
 
-// EXACT: g was exponentiated exactly beforehand (k_gauge_exp) and is read as
-// rows 0,1 from GX (6 entries per site) instead of being formed from L Delta.
-template <class T, class TF, bool ACC_G, bool EXACT, int NR>
+// GPRE: each site's transformation was computed beforehand and is read as
+// rows 0,1 from GX (6 entries per site) instead of being formed from L Delta:
+// g = exp((alpha/2) L Delta) of the exact step (k_gauge_exp), or the
+// accumulated G of the FP32 sweeps (k_gauge_acc), whose links G U0 G^dagger
+// come from the constant input copy U0 in Lin.  STORE: write the new links to
+// Lout (the FP32 sweeps keep U0 and G instead).
+template <class T, class TF, bool GPRE, int NR, bool STORE>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_update(geom g, const vec2_t<T> *__restrict__ Lin, vec2_t<T> *__restrict__ Lout,
              const vec2_t<TF> *__restrict__ LD, const vec2_t<T> *__restrict__ GX,
-             vec2_t<TF> *__restrict__ Dout, vec2_t<T> *__restrict__ G, T c,
-             double *__restrict__ partials, const dev_status *__restrict__ status) {
+             vec2_t<TF> *__restrict__ Dout, T c, double *__restrict__ partials,
+             const dev_status *__restrict__ status) {
     if (status->done) return;
     const long s = block_site(g, blockIdx.x, gridDim.x, threadIdx.x);
     double fs = 0, ts = 0;
@@ -215,24 +219,24 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         const nbr n = neighbours(g, s);
         // Eight half-steps h = 2 mu + b: b = 0 transforms the link U_mu(x)
         // with g(x+mu), b = 1 the link U_mu(x-mu) with g(x-mu).  Each needs
-        // the 4 field entries of g's site (6 entries of g itself when EXACT)
+        // the 4 field entries of g's site (6 entries of g itself when GPRE)
         // and 3*NR link entries; the loads of half-step h+1 are issued before
         // half-step h is computed (software pipelining), so every wave keeps
         // the next memory round trip in flight.
-        constexpr int NG = EXACT ? 6 : 4;
+        constexpr int NG = GPRE ? 6 : 4;
         struct half {
             cpx<T> f[NG], u[3 * NR];
         };
         auto load_g = [&](long x, cpx<T> (&f)[NG]) {
 #pragma unroll
             for (int k = 0; k < NG; ++k) {
-                if constexpr (EXACT) f[k] = ld<T>(GX + (long)k * g.S + x);
+                if constexpr (GPRE) f[k] = ld<T>(GX + (long)k * g.S + x);
                 else f[k] = cvt<T>(ld<TF>(LD + (long)k * g.S + x));
             }
         };
         auto make_g = [&](const cpx<T> (&f)[NG]) {
             mat3<T> m;
-            if constexpr (EXACT) {
+            if constexpr (GPRE) {
 #pragma unroll
                 for (int k = 0; k < 6; ++k) m.e[k / 3][k % 3] = f[k];
                 rebuild_row2(m);
@@ -270,7 +274,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
             if constexpr (NR == 2) rebuild_row2(u);
             if ((h & 1) == 0) {
                 const mat3<T> un = mul_abcd<NR>(g0, u, gn);  // g(x) U_mu(x) g(x+mu)^+
-                store_link<T, NR>(Lout, g.S, h >> 1, s, un);
+                if constexpr (STORE) store_link<T, NR>(Lout, g.S, h >> 1, s, un);
                 tr += retrace(un);
                 xacc_add(X, un, T(-1));
             } else {
@@ -285,22 +289,6 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         st_stream<TF>(Dout + g.S + s, cvt<TF>(f1));
         st_stream<TF>(Dout + 2 * g.S + s, cvt<TF>(f2));
         st_stream<TF>(Dout + 3 * g.S + s, cvt<TF>(f3));
-        if constexpr (ACC_G) {
-            // G(x) <- g(x) G(x), rows 0,1 kept (12 reals)
-            mat3<T> G0;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) G0.e[k / 3][k % 3] = ld<T>(G + (long)k * g.S + s);
-            rebuild_row2(G0);
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    cpx<T> acc = cmul(g0.e[i][0], G0.e[0][j]);
-                    acc = cmac(acc, g0.e[i][1], G0.e[1][j]);
-                    acc = cmac(acc, g0.e[i][2], G0.e[2][j]);
-                    st<T>(G + (long)(3 * i + j) * g.S + s, acc);
-                }
-        }
     }
     block_sum2<SITE_BLOCK>(fs, ts, partials, blockIdx.x);
 }
@@ -752,6 +740,36 @@ __global__ void __launch_bounds__(256)
     for (int k = 0; k < 6; ++k) st<T>(GX + (long)k * g.S + s, m.e[k / 3][k % 3]);
 }
 
+// FP32 sweeps of a mixed solve: G(x) <- g(x) G(x), rows 0,1 kept (12 reals),
+// from Gold into Gnew (the update then forms G(x) U0 G(x+mu)^dagger at x and
+// its neighbours from Gnew; the old G stays readable for those neighbours).
+template <class T, class TF, bool EXACT>
+__global__ void __launch_bounds__(256)
+    k_gauge_acc(geom g, const vec2_t<TF> *__restrict__ LD, const vec2_t<T> *__restrict__ Gold,
+                vec2_t<T> *__restrict__ Gnew, T c, const dev_status *__restrict__ status) {
+    if (status->done) return;
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.V) return;
+    const cpx<T> f0 = cvt<T>(ld<TF>(LD + s)), f1 = cvt<T>(ld<TF>(LD + g.S + s)),
+                 f2 = cvt<T>(ld<TF>(LD + 2 * g.S + s)), f3 = cvt<T>(ld<TF>(LD + 3 * g.S + s));
+    mat3<T> gx;
+    if constexpr (EXACT) gx = gauge_exp_from_entries<T>(f0, f1, f2, f3, c);
+    else gx = gauge_from_entries<T>(f0, f1, f2, f3, c);
+    mat3<T> G0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) G0.e[k / 3][k % 3] = ld<T>(Gold + (long)k * g.S + s);
+    rebuild_row2(G0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cpx<T> acc = cmul(gx.e[i][0], G0.e[0][j]);
+            acc = cmac(acc, gx.e[i][1], G0.e[1][j]);
+            acc = cmac(acc, gx.e[i][2], G0.e[2][j]);
+            st<T>(Gnew + (long)(3 * i + j) * g.S + s, acc);
+        }
+}
+
 // The Fourier field is FP32 for FP32 sweeps and, when g.ff32 is set, for FP64
 // sweeps too; f(tag) runs the body with the field's real type.
 template <class T, class Body> hipError_t with_field_type(const geom &g, Body f) {
@@ -800,24 +818,38 @@ hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void 
         if (g.nc == 2)
             return launch_update_su2<T, TF>(g, Lin, Lout, LD, Dout, G, c, exact, partials, status,
                                             st);
-        if (exact) {
+        auto LDp = static_cast<const vec2_t<TF> *>(LD);
+        if (ACC || exact) {
             if (!GX) return hipErrorInvalidValue;
-            k_gauge_exp<T, TF><<<nblk(g.V, 256), 256, 0, st>>>(
-                g, static_cast<const vec2_t<TF> *>(LD), static_cast<vec2_t<T> *>(GX), c, status);
+            auto GXp = static_cast<vec2_t<T> *>(GX);
+            if constexpr (ACC) {
+                auto Gp = static_cast<const vec2_t<T> *>(G);
+                if (exact)
+                    k_gauge_acc<T, TF, true><<<nblk(g.V, 256), 256, 0, st>>>(g, LDp, Gp, GXp, c,
+                                                                            status);
+                else
+                    k_gauge_acc<T, TF, false><<<nblk(g.V, 256), 256, 0, st>>>(g, LDp, Gp, GXp, c,
+                                                                             status);
+            } else {
+                k_gauge_exp<T, TF><<<nblk(g.V, 256), 256, 0, st>>>(g, LDp, GXp, c, status);
+            }
         }
         auto go = [&](auto kernel) {
             kernel<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
-                g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout),
-                static_cast<const vec2_t<TF> *>(LD), static_cast<const vec2_t<T> *>(GX),
-                static_cast<vec2_t<TF> *>(Dout), static_cast<vec2_t<T> *>(G), c, partials,
+                g, static_cast<const vec2_t<T> *>(Lin), static_cast<vec2_t<T> *>(Lout), LDp,
+                static_cast<const vec2_t<T> *>(GX), static_cast<vec2_t<TF> *>(Dout), c, partials,
                 status);
         };
-        if (g.nr == 3) {
-            if (exact) go(k_update<T, TF, ACC, true, 3>);
-            else go(k_update<T, TF, ACC, false, 3>);
+        if constexpr (ACC) {
+            // links G U0 G^dagger from the constant copy U0 (Lin), not stored
+            if (g.nr == 3) go(k_update<T, TF, true, 3, false>);
+            else go(k_update<T, TF, true, 2, false>);
+        } else if (g.nr == 3) {
+            if (exact) go(k_update<T, TF, true, 3, true>);
+            else go(k_update<T, TF, false, 3, true>);
         } else {
-            if (exact) go(k_update<T, TF, ACC, true, 2>);
-            else go(k_update<T, TF, ACC, false, 2>);
+            if (exact) go(k_update<T, TF, true, 2, true>);
+            else go(k_update<T, TF, false, 2, true>);
         }
         return hipGetLastError();
     });

@@ -210,16 +210,38 @@ hipError_t transform_pass(lgf_ctx *c, bool f32, int pass, void *D) {
     return launch_fft_xy<double>(c->g, D, +1, c->tw64, c->status, c->stream);
 }
 
+// Pass `pass` (0..2) of sweep `cur`'s transform of field D (none without the
+// acceleration).  In the FP32 sweeps of an SU(3) mixed solve pass 2 also
+// accumulates G <- g G: fused into the inverse (x,y) pass when that is a
+// register-column one, else as a kernel after it.
+template <class T>
+hipError_t sweep_pass(lgf_ctx *c, int cur, void *D, T half_alpha, int pass) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (c->g.nc == 3 && pass == 2) {
+            if (c->accelerate && xy_acc_fusable<float>(c->g))
+                return launch_fft_xy_inv_acc<float>(c->g, D, c->tw32, acc_G(c, cur),
+                                                    acc_G(c, cur ^ 1), half_alpha, c->exact_exp,
+                                                    c->status, c->stream);
+            if (c->accelerate) {
+                const hipError_t e = transform_pass(c, true, 2, D);
+                if (e != hipSuccess) return e;
+            }
+            return launch_gauge_acc(c->g, D, acc_G(c, cur), acc_G(c, cur ^ 1), half_alpha,
+                                    c->exact_exp, c->status, c->stream);
+        }
+    }
+    if (!c->accelerate) return hipSuccess;
+    return transform_pass(c, field32<T>(c), pass, D);
+}
+
 // One Fourier-accelerated sweep from links/field buffer `cur` into `cur^1`.
 template <class T>
 hipError_t enqueue_sweep(lgf_ctx *c, int cur, T half_alpha, const fin_params &fp) {
     using P = prec<T>;
     hipError_t e;
     void *D = P::field(c, cur);
-    if (c->accelerate) {
-        for (int pass = 0; pass < 3; ++pass)
-            if ((e = transform_pass(c, field32<T>(c), pass, D)) != hipSuccess) return e;
-    }
+    for (int pass = 0; pass < 3; ++pass)
+        if ((e = sweep_pass<T>(c, cur, D, half_alpha, pass)) != hipSuccess) return e;
     return sweep_update<T>(c, cur, D, half_alpha, fp);
 }
 
@@ -375,11 +397,11 @@ int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
         hipError_t err = hipSuccess;
         auto chk = [&](hipError_t x) { if (err == hipSuccess) err = x; };
         chk(hipEventRecord(e[0], c->stream));
-        chk(transform_pass(c, field32<T>(c), 0, D));
+        chk(sweep_pass<T>(c, cur, D, half_alpha, 0));
         chk(hipEventRecord(e[1], c->stream));
-        chk(transform_pass(c, field32<T>(c), 1, D));
+        chk(sweep_pass<T>(c, cur, D, half_alpha, 1));
         chk(hipEventRecord(e[2], c->stream));
-        chk(transform_pass(c, field32<T>(c), 2, D));
+        chk(sweep_pass<T>(c, cur, D, half_alpha, 2));
         chk(hipEventRecord(e[3], c->stream));
         chk(sweep_update<T>(c, cur, D, half_alpha, finp(c, false)));
         chk(hipEventRecord(e[4], c->stream));

@@ -252,6 +252,63 @@ __global__ void __launch_bounds__(rc_max_threads<T>())
     for (int y = 0; y < NY; ++y) st<T>(p + (long)y * Lx, a[y]);
 }
 
+// Inverse (x, y) pass of the FP32 sweeps of an SU(3) mixed solve, fused with
+// the accumulation G(x) <- g(x) G(x): the block holds all 4 fields of its
+// plane, so after the inverse transform each site's 4 entries of L Delta are
+// gathered through LDS, g is formed (first-order or exact step, coefficient
+// c) and G is updated from Gold into Gnew.  L Delta itself is not stored (the
+// update reads only G).
+template <class T, int NY, bool EXACT>
+__global__ void __launch_bounds__(rc_max_threads<T>())
+    k_fft_xy_rc_acc(geom g, const vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
+                    const vec2_t<T> *__restrict__ Gold, vec2_t<T> *__restrict__ Gnew, T c,
+                    const dev_status *__restrict__ status) {
+    if (status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
+    constexpr int F = 4;
+    const int Lx = g.Lx;
+    const long Lxy = (long)Lx * NY;
+    const int x = threadIdx.x % Lx, fl = threadIdx.x / Lx;
+    const int SW = Lx + 1, PJ = F * SW;
+    const vec2_t<T> *p = D + (long)fl * g.S + (long)blockIdx.x * Lxy + x;
+    cpx<T> a[NY];
+#pragma unroll
+    for (int y = 0; y < NY; ++y) a[y] = ld<T>(p + (long)y * Lx);
+    auto base = [SW, PJ](int cc) { return (cc / F) * PJ + (cc % F) * SW; };  // cc = fl + F*j
+    auto col = [&](int, int C) { col_fft_small<+1, T>(Lx, lds, F * C, 1, base, tw); };
+    exchange_axis<NY, T>(a, fl, x, 1, SW, PJ, lds, col);
+    dft<NY, +1>(a, tw);
+    __syncthreads();  // every thread has read its column back
+#pragma unroll
+    for (int y = 0; y < NY; ++y) st<T>(lds + y * PJ + fl * SW + x, a[y]);
+    __syncthreads();
+    const long s0 = (long)blockIdx.x * Lxy;
+    for (int i = threadIdx.x; i < (int)Lxy; i += blockDim.x) {
+        const int y = i / Lx, xx = i - y * Lx;
+        const vec2_t<T> *q = lds + y * PJ + xx;
+        const cpx<T> f0 = ld<T>(q), f1 = ld<T>(q + SW), f2 = ld<T>(q + 2 * SW),
+                     f3 = ld<T>(q + 3 * SW);
+        mat3<T> gx;
+        if constexpr (EXACT) gx = gauge_exp_from_entries<T>(f0, f1, f2, f3, c);
+        else gx = gauge_from_entries<T>(f0, f1, f2, f3, c);
+        const long s = s0 + i;
+        mat3<T> G0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) G0.e[k / 3][k % 3] = ld<T>(Gold + (long)k * g.S + s);
+        rebuild_row2(G0);
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                cpx<T> acc = cmul(gx.e[r][0], G0.e[0][j]);
+                acc = cmac(acc, gx.e[r][1], G0.e[1][j]);
+                acc = cmac(acc, gx.e[r][2], G0.e[2][j]);
+                st<T>(Gnew + (long)(3 * r + j) * g.S + s, acc);
+            }
+    }
+}
+
 // (z, t) pass: W consecutive xy-sites of one field per block, thread (w, z)
 // holds a t-column.  MODE 0: forward, scale by p2max/(V p2), inverse.
 template <class T, int NT, int MODE>
@@ -349,6 +406,39 @@ hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const 
         if (dir < 0) k_fft_xy<T, -1, 32><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
         else k_fft_xy<T, +1, 32><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
     }
+    return hipGetLastError();
+}
+
+// The fused inverse (x,y) pass with G accumulation: register-column planes
+// holding all 4 fields in one block.
+template <class T> inline bool xy_acc_fusable(const geom &g) {
+    return g.nc == 3 && g.nf == 4 && xy_use_rc<T>(g) && xy_fields_per_block<T>(g) == 4;
+}
+
+template <class T>
+hipError_t launch_fft_xy_inv_acc(const geom &g, void *D, const void *tw, const void *Gold,
+                                 void *Gnew, T c, bool exact, const dev_status *status,
+                                 hipStream_t st) {
+    if (!xy_acc_fusable<T>(g)) return hipErrorInvalidValue;
+    auto Dp = static_cast<const vec2_t<T> *>(D);
+    auto twp = static_cast<const vec2_t<T> *>(tw);
+    auto Go = static_cast<const vec2_t<T> *>(Gold);
+    auto Gn = static_cast<vec2_t<T> *>(Gnew);
+    const size_t lds = fft_xy_lds_bytes<T>(g);
+    const dim3 grid((unsigned)(g.Lz * g.Lt));
+    const unsigned nt = (unsigned)(4 * g.Lx);
+#define LGF_XA(NN)                                                                            \
+    case NN:                                                                                  \
+        if (exact)                                                                            \
+            k_fft_xy_rc_acc<T, NN, true><<<grid, nt, lds, st>>>(g, Dp, twp, Go, Gn, c, status);  \
+        else                                                                                  \
+            k_fft_xy_rc_acc<T, NN, false><<<grid, nt, lds, st>>>(g, Dp, twp, Go, Gn, c, status); \
+        break;
+    switch (g.Ly) {
+        LGF_NA_CASES(LGF_XA)
+    default: return hipErrorInvalidValue;
+    }
+#undef LGF_XA
     return hipGetLastError();
 }
 

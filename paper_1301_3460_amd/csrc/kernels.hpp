@@ -78,10 +78,11 @@ hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *part
 // 6 complex entries per site, stride S; SU(2) evaluates it in the update).
 // T = float (the FP32 sweeps of a mixed solve): G is the accumulated
 // transformation.  SU(3): Lin holds the constant FP32 copy U0 of the input
-// links, G the transformation before the sweep and GX receives it after
-// (g(x) G(x), rows 0,1); the new links G U0 G^dagger are formed in the update
-// and not stored (Lout unused).  SU(2): links go from Lin to Lout and G is
-// updated in place.
+// links and GX the transformation after this sweep's step (g(x) G(x), rows
+// 0,1, accumulated beforehand by launch_fft_xy_inv_acc or launch_gauge_acc;
+// G is the one before it, only checked); the new links G U0 G^dagger are
+// formed in the update and not stored (Lout unused).  SU(2): links go from
+// Lin to Lout and G is updated in place.
 template <class T>
 hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void *LD, void *Dout,
                          void *G, T c, bool exact, void *GX, double *partials, dev_status *status,
@@ -101,6 +102,18 @@ struct zt_plan {
     int Wz = 1, Wt = 1, Bz = 1, Bt = 1;
     size_t ldsz = 0, ldst = 0;
 };
+// Inverse (x,y) pass fused with G(x) <- g(x) G(x) (FP32 sweeps of an SU(3)
+// mixed solve; L Delta itself is not stored), when xy_acc_fusable: register-
+// column planes with all 4 fields in one block.
+template <class T> bool xy_acc_fusable(const geom &g);
+template <class T>
+hipError_t launch_fft_xy_inv_acc(const geom &g, void *D, const void *tw, const void *Gold,
+                                 void *Gnew, T c, bool exact, const dev_status *status,
+                                 hipStream_t st);
+// G(x) <- g(x) G(x) from the field L Delta as a kernel of its own (FP32 sweeps
+// of an SU(3) mixed solve whose inverse (x,y) pass cannot take it)
+hipError_t launch_gauge_acc(const geom &g, const void *LD, const void *Gold, void *Gnew, float c,
+                            bool exact, const dev_status *status, hipStream_t st);
 template <class T> zt_plan plan_zt(const geom &g, size_t lds_budget);
 template <class T> size_t fft_xy_lds_bytes(const geom &g);
 template <class T> void fft_set_max_lds(const geom &g, const zt_plan &p);

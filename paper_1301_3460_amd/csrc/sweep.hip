@@ -821,18 +821,10 @@ hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void 
         auto LDp = static_cast<const vec2_t<TF> *>(LD);
         if (ACC || exact) {
             if (!GX) return hipErrorInvalidValue;
-            auto GXp = static_cast<vec2_t<T> *>(GX);
-            if constexpr (ACC) {
-                auto Gp = static_cast<const vec2_t<T> *>(G);
-                if (exact)
-                    k_gauge_acc<T, TF, true><<<nblk(g.V, 256), 256, 0, st>>>(g, LDp, Gp, GXp, c,
-                                                                            status);
-                else
-                    k_gauge_acc<T, TF, false><<<nblk(g.V, 256), 256, 0, st>>>(g, LDp, Gp, GXp, c,
-                                                                             status);
-            } else {
-                k_gauge_exp<T, TF><<<nblk(g.V, 256), 256, 0, st>>>(g, LDp, GXp, c, status);
-            }
+            // FP32: GX already holds g G (launch_fft_xy_inv_acc / launch_gauge_acc)
+            if constexpr (!ACC)
+                k_gauge_exp<T, TF><<<nblk(g.V, 256), 256, 0, st>>>(
+                    g, LDp, static_cast<vec2_t<T> *>(GX), c, status);
         }
         auto go = [&](auto kernel) {
             kernel<<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(
@@ -857,6 +849,19 @@ hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void 
     if (fp.enabled) k_finalize<<<1, FIN_BLOCK, 0, st>>>(partials, site_blocks(g.V), status, fp);
     return hipGetLastError();
 }
+hipError_t launch_gauge_acc(const geom &g, const void *LD, const void *Gold, void *Gnew, float c,
+                            bool exact, const dev_status *status, hipStream_t st) {
+    if (g.nc != 3) return hipErrorInvalidValue;
+    auto LDp = static_cast<const float2 *>(LD);
+    auto Go = static_cast<const float2 *>(Gold);
+    auto Gn = static_cast<float2 *>(Gnew);
+    if (exact)
+        k_gauge_acc<float, float, true><<<nblk(g.V, 256), 256, 0, st>>>(g, LDp, Go, Gn, c, status);
+    else
+        k_gauge_acc<float, float, false><<<nblk(g.V, 256), 256, 0, st>>>(g, LDp, Go, Gn, c, status);
+    return hipGetLastError();
+}
+
 template hipError_t launch_update<double>(const geom &, const void *, void *, const void *, void *,
                                           void *, double, bool, void *, double *, dev_status *,
                                           const fin_params &, hipStream_t);

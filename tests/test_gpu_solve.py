@@ -35,6 +35,10 @@ def _check_solution(Uout, Uin, tol, F):
     ((4, 4, 4, 4), 0.5, inputs.CONFIG_SEEDS[("4^4", 0.5)], 1e-15),
     ((4, 6, 8, 12), 0.45, 77, 1e-15),
     ((6, 6, 6, 6), 0.6, 78, 1e-14),
+    # 32-wide planes (FP32 sweeps accumulate G inside the inverse (x,y) pass)
+    # and 48-wide ones (a separate accumulation kernel)
+    ((32, 8, 4, 4), 0.5, 80, 1e-14),
+    ((48, 4, 4, 6), 0.5, 79, 1e-14),
 ])
 def test_solve_matches_oracle(lgf_gpu, L, eps, seed, tol, precision):
     U, _ = inputs.make_config(L, eps, seed)
@@ -173,8 +177,10 @@ def test_exact_exp_lockstep(lgf_gpu, L, accelerate):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_exact_exp_solve_matches_oracle(lgf_gpu, precision):
-    U, _ = inputs.make_config((8, 8, 8, 8), 0.5, inputs.CONFIG_SEEDS[("8^4", 0.5)])
+@pytest.mark.parametrize("L,seed", [((8, 8, 8, 8), inputs.CONFIG_SEEDS[("8^4", 0.5)]),
+                                    ((48, 4, 4, 6), 81)])
+def test_exact_exp_solve_matches_oracle(lgf_gpu, precision, L, seed):
+    U, _ = inputs.make_config(L, 0.5, seed)
     ref = oracle.fix(U, ALPHA, 1e-14, 1000, exact_exp=True)
     assert ref["status"] == 0
     Ug = gpu(U)

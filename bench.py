@@ -29,13 +29,17 @@ EPS_MAIN = 0.45
 BYTES_UPDATE_18 = 4 * 144 * 2 + 128  # update with 18-real links: R+W 4 x 144 B, R+W 64 B
 BYTES_UPDATE_SU2 = 4 * 32 * 2 + 32 * 2  # SU(2) update: R+W 4 links x 32 B, R+W 2 fields
 SD_TOL = 1e-10  # plain steepest descent needs thousands of sweeps at 32^4
-# algorithmic bytes per site of each sweep kernel (FP64; FP32 sweeps of a
-# mixed solve, whose "update" is G <- g G (R field 32, R+W G 96) followed by
-# the update from the input copy U0 (R U0 192, R G 48, W field 32))
+# algorithmic bytes per site of each sweep kernel: FP64, and the FP32 sweeps
+# of a mixed solve, whose inverse (x,y) pass also does G <- g G (R field 32,
+# R+W G 96, the field itself not written back) and whose update forms the
+# links from the input copy U0 (R U0 192, R G 48, W field 32).  On planes
+# wider than 32 the accumulation is a kernel of its own after a plain inverse
+# pass (64 + 32 + 96).
 BYTES_PER_SITE = {
     "fp64": {"fft_xy_fwd": 128, "fft_zt": 128, "fft_xy_inv": 128, "update": 896, "finalize": 0},
-    "fp32": {"fft_xy_fwd": 64, "fft_zt": 64, "fft_xy_inv": 64, "update": 128 + 272, "finalize": 0},
+    "fp32": {"fft_xy_fwd": 64, "fft_zt": 64, "fft_xy_inv": 128, "update": 272, "finalize": 0},
 }
+BYTES_XY_INV_ACC_SEPARATE = 64 + 32 + 96
 
 
 # sources that determine the update kernel's code (for the traffic record)
@@ -159,10 +163,13 @@ def main() -> int:
     prof64 = ctx64.profile(U0, ALPHA, 50)
     prof32 = ctx32.profile(U0, ALPHA, 50)
     per_kernel = {}
-    for name, prof, key in (("fp64", prof64, "fp64"), ("fp32", prof32, "fp32")):
+    fp32_bytes = dict(BYTES_PER_SITE["fp32"])
+    if Lrun[0] > 32 or Lrun[1] > 32:
+        fp32_bytes["fft_xy_inv"] = BYTES_XY_INV_ACC_SEPARATE
+    for name, prof, nbytes in (("fp64", prof64, BYTES_PER_SITE["fp64"]), ("fp32", prof32, fp32_bytes)):
         per_kernel[name] = {
             k: {"ms": round(v, 5),
-                "GBps": round(BYTES_PER_SITE[key][k] * V / (v * 1e-3) / 1e9, 1) if v > 0 else None}
+                "GBps": round(nbytes[k] * V / (v * 1e-3) / 1e9, 1) if v > 0 else None}
             for k, v in prof.items()}
     log("per-kernel:", json.dumps(per_kernel))
     upd_ms = prof64["update"]

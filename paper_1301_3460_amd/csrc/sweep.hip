@@ -99,12 +99,28 @@ __global__ void k_matrix_from_field(const double2 *__restrict__ D, double2 *__re
 constexpr int FIN_BLOCK = 1024;
 
 template <int NT>
-__device__ __forceinline__ void fixed_order_sum(const volatile double *partials, int nparts,
+__device__ __forceinline__ void fixed_order_sum(const double *__restrict__ partials, int nparts,
                                                 double &A, double &B) {
+    // thread t adds pairs t, t + NT, t + 2 NT, ... in that order; four 16-byte
+    // loads are in flight per step
+    const double2 *p2 = reinterpret_cast<const double2 *>(partials);
     double a = 0, b = 0;
-    for (int i = threadIdx.x; i < nparts; i += NT) {
-        a += partials[2 * i];
-        b += partials[2 * i + 1];
+    int i = threadIdx.x;
+    for (; i + 3 * NT < nparts; i += 4 * NT) {
+        const double2 v0 = p2[i], v1 = p2[i + NT], v2 = p2[i + 2 * NT], v3 = p2[i + 3 * NT];
+        a += v0.x;
+        b += v0.y;
+        a += v1.x;
+        b += v1.y;
+        a += v2.x;
+        b += v2.y;
+        a += v3.x;
+        b += v3.y;
+    }
+    for (; i < nparts; i += NT) {
+        const double2 v = p2[i];
+        a += v.x;
+        b += v.y;
     }
     __shared__ double sa[NT], sb[NT];
     sa[threadIdx.x] = a;

@@ -11,7 +11,10 @@
 //               block partial sums of F and theta
 //   finalize    fixed-order sum of the partials, stopping test
 // Links are double-buffered (the update reads U_mu(x-mu) of other threads),
-// as are the Fourier fields.
+// as are the Fourier fields.  The FP32 sweeps of an SU(3) mixed solve store
+// no links: their inverse (x, y) pass (or k_gauge_acc after it) turns L Delta
+// into G <- g G, double-buffered, and the update forms G U0 G^dagger from the
+// constant input copy U0.
 #include <type_traits>
 
 #include "common.hpp"

@@ -7,6 +7,8 @@
 //   k_fft_axis                 one axis of the (z,t) plane per pass, W sites
 //                              x the axis x B slices in LDS (larger extents)
 #pragma once
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace lgf {
@@ -70,6 +72,59 @@ __global__ void __launch_bounds__(XY_BLOCK)
     for (int i = threadIdx.x; i < Lxy; i += XY_BLOCK) {
         const int y = i / Lx, x = i - y * Lx;
         plane[i] = lds[y * P + x];
+    }
+}
+
+// Inverse (x, y) pass of the FP32 sweeps of an SU(3) mixed solve on planes
+// wider than 32, fused with G(x) <- g(x) G(x): one plane of all 4 fields per
+// block (4 LDS regions [y][x+1]); after the transform each site's 4 entries
+// of L Delta are read from the regions, g is formed and G goes from Gold into
+// Gnew.  L Delta itself is not stored.
+template <class T, int RMAX, bool EXACT>
+__global__ void __launch_bounds__(XY_BLOCK)
+    k_fft_xy_acc(geom g, const vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
+                 const vec2_t<T> *__restrict__ Gold, vec2_t<T> *__restrict__ Gnew, T c,
+                 const dev_status *__restrict__ status) {
+    if (status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
+    const int Lx = g.Lx, Ly = g.Ly, P = Lx + 1, REG = Ly * P;
+    const int Lxy = Lx * Ly;
+    const long s0 = (long)blockIdx.x * Lxy;
+    for (int f = 0; f < 4; ++f)
+        for (int i = threadIdx.x; i < Lxy; i += XY_BLOCK) {
+            const int y = i / Lx, x = i - y * Lx;
+            lds[f * REG + y * P + x] = D[(long)f * g.S + s0 + i];
+        }
+    __syncthreads();
+    auto cols = [Lx, REG](int cc) { return (cc / Lx) * REG + (cc % Lx); };      // cc = x + Lx f
+    auto rows = [Ly, REG, P](int cc) { return (cc / Ly) * REG + (cc % Ly) * P; };  // cc = y + Ly f
+    lds_axis_fft<+1, T, RMAX>(Ly, lds, 4 * Lx, P, cols, tw);
+    __syncthreads();
+    lds_axis_fft<+1, T, RMAX>(Lx, lds, 4 * Ly, 1, rows, tw);
+    __syncthreads();
+    for (int i = threadIdx.x; i < Lxy; i += XY_BLOCK) {
+        const int y = i / Lx, x = i - y * Lx;
+        const vec2_t<T> *q = lds + y * P + x;
+        const cpx<T> f0 = ld<T>(q), f1 = ld<T>(q + REG), f2 = ld<T>(q + 2 * REG),
+                     f3 = ld<T>(q + 3 * REG);
+        mat3<T> gx;
+        if constexpr (EXACT) gx = gauge_exp_from_entries<T>(f0, f1, f2, f3, c);
+        else gx = gauge_from_entries<T>(f0, f1, f2, f3, c);
+        const long s = s0 + i;
+        mat3<T> G0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) G0.e[k / 3][k % 3] = ld<T>(Gold + (long)k * g.S + s);
+        rebuild_row2(G0);
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                cpx<T> acc = cmul(gx.e[r][0], G0.e[0][j]);
+                acc = cmac(acc, gx.e[r][1], G0.e[1][j]);
+                acc = cmac(acc, gx.e[r][2], G0.e[2][j]);
+                st<T>(Gnew + (long)(3 * r + j) * g.S + s, acc);
+            }
     }
 }
 
@@ -411,8 +466,14 @@ hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const 
 
 // The fused inverse (x,y) pass with G accumulation: register-column planes
 // holding all 4 fields in one block.
+constexpr size_t XY_ACC_LDS_MAX = 150 * 1024;
+template <class T> inline size_t xy_acc_lds_bytes(const geom &g) {
+    return (size_t)4 * g.Ly * (g.Lx + 1) * sizeof(vec2_t<T>);
+}
 template <class T> inline bool xy_acc_fusable(const geom &g) {
-    return g.nc == 3 && g.nf == 4 && xy_use_rc<T>(g) && xy_fields_per_block<T>(g) == 4;
+    if (g.nc != 3 || g.nf != 4) return false;
+    if (xy_use_rc<T>(g)) return xy_fields_per_block<T>(g) == 4;
+    return xy_acc_lds_bytes<T>(g) <= XY_ACC_LDS_MAX;
 }
 
 template <class T>
@@ -424,6 +485,21 @@ hipError_t launch_fft_xy_inv_acc(const geom &g, void *D, const void *tw, const v
     auto twp = static_cast<const vec2_t<T> *>(tw);
     auto Go = static_cast<const vec2_t<T> *>(Gold);
     auto Gn = static_cast<vec2_t<T> *>(Gnew);
+    if (!xy_use_rc<T>(g)) {
+        const size_t b = xy_acc_lds_bytes<T>(g);
+        const dim3 grid((unsigned)(g.Lz * g.Lt));
+        const bool sm = fft_reg_span(g.Lx) <= 16 && fft_reg_span(g.Ly) <= 16;
+#define LGF_XG(R, E) k_fft_xy_acc<T, R, E><<<grid, XY_BLOCK, b, st>>>(g, Dp, twp, Go, Gn, c, status)
+        if (sm) {
+            if (exact) LGF_XG(16, true);
+            else LGF_XG(16, false);
+        } else {
+            if (exact) LGF_XG(32, true);
+            else LGF_XG(32, false);
+        }
+#undef LGF_XG
+        return hipGetLastError();
+    }
     const size_t lds = fft_xy_lds_bytes<T>(g);
     const dim3 grid((unsigned)(g.Lz * g.Lt));
     const unsigned nt = (unsigned)(4 * g.Lx);
@@ -517,6 +593,15 @@ template <class T> void fft_set_max_lds(const geom &g, const zt_plan &p) {
         set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, 0, 32>), p.ldst);
         set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, -1, 32>), p.ldst);
         set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, 1, 32>), p.ldst);
+    }
+    if constexpr (std::is_same<T, float>::value) {
+        if (!xy_use_rc<T>(g) && xy_acc_fusable<T>(g)) {
+            const size_t b = xy_acc_lds_bytes<T>(g);
+            set(reinterpret_cast<const void *>(&k_fft_xy_acc<T, 16, true>), b);
+            set(reinterpret_cast<const void *>(&k_fft_xy_acc<T, 16, false>), b);
+            set(reinterpret_cast<const void *>(&k_fft_xy_acc<T, 32, true>), b);
+            set(reinterpret_cast<const void *>(&k_fft_xy_acc<T, 32, false>), b);
+        }
     }
     if (!xy_use_rc<T>(g)) {
         const size_t b = fft_xy_lds_bytes<T>(g);

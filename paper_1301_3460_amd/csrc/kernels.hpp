@@ -104,7 +104,8 @@ struct zt_plan {
 };
 // Inverse (x,y) pass fused with G(x) <- g(x) G(x) (FP32 sweeps of an SU(3)
 // mixed solve; L Delta itself is not stored), when xy_acc_fusable: register-
-// column planes with all 4 fields in one block.
+// column planes with all 4 fields in one block, or wider planes whose 4
+// fields fit in LDS together.
 template <class T> bool xy_acc_fusable(const geom &g);
 template <class T>
 hipError_t launch_fft_xy_inv_acc(const geom &g, void *D, const void *tw, const void *Gold,

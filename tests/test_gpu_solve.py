@@ -35,10 +35,12 @@ def _check_solution(Uout, Uin, tol, F):
     ((4, 4, 4, 4), 0.5, inputs.CONFIG_SEEDS[("4^4", 0.5)], 1e-15),
     ((4, 6, 8, 12), 0.45, 77, 1e-15),
     ((6, 6, 6, 6), 0.6, 78, 1e-14),
-    # 32-wide planes (FP32 sweeps accumulate G inside the inverse (x,y) pass)
-    # and 48-wide ones (a separate accumulation kernel)
+    # planes where the FP32 sweeps accumulate G inside the inverse (x,y) pass:
+    # register columns (32 wide), and the 4-field LDS kernel for wider planes
+    # with register spans up to 16 (48 wide) and 32 (Ly = 48 beside Lx = 32)
     ((32, 8, 4, 4), 0.5, 80, 1e-14),
     ((48, 4, 4, 6), 0.5, 79, 1e-14),
+    ((32, 48, 2, 2), 0.5, 82, 1e-14),
 ])
 def test_solve_matches_oracle(lgf_gpu, L, eps, seed, tol, precision):
     U, _ = inputs.make_config(L, eps, seed)
@@ -144,6 +146,18 @@ def test_plain_steepest_descent_lockstep(lgf_gpu, L):
         ref = oracle.fix(U, ALPHA, 0.0, 1, accelerate=False)["U"]
         assert np.max(np.abs(got - ref)) < 1e-13, step
         U = got
+
+
+def test_plain_steepest_descent_mixed(lgf_gpu):
+    """Without the transform the FP32 sweeps accumulate G in a kernel of its own."""
+    U, _ = inputs.make_config((4, 4, 4, 4), 0.5, 83)
+    ref = oracle.fix(U, ALPHA, 1e-12, 3000, accelerate=False)
+    assert ref["status"] == 0
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, ALPHA, 1e-12, precision="mixed", max_iter=3000, accelerate=False)
+    assert r.status == 0 and 0 < r.fp32_iterations < r.iterations
+    _check_solution(cpu(Ug), U, 1e-12, r.F)
+    assert abs(r.F - ref["F"]) < 1e-12
 
 
 def test_plain_steepest_descent_solve(lgf_gpu):

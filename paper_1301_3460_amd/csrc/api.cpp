@@ -212,8 +212,8 @@ hipError_t transform_pass(lgf_ctx *c, bool f32, int pass, void *D) {
 
 // Pass `pass` (0..2) of sweep `cur`'s transform of field D (none without the
 // acceleration).  In the FP32 sweeps of an SU(3) mixed solve pass 2 also
-// accumulates G <- g G: fused into the inverse (x,y) pass when that is a
-// register-column one, else as a kernel after it.
+// accumulates G <- g G: fused into the inverse (x,y) pass when one block can
+// hold a plane of all four fields (xy_acc_fusable), else as a kernel after it.
 template <class T>
 hipError_t sweep_pass(lgf_ctx *c, int cur, void *D, T half_alpha, int pass) {
     if constexpr (std::is_same<T, float>::value) {

@@ -256,13 +256,18 @@ int read_status(lgf_ctx *c, dev_status &out) {
 // Runs one precision phase on the working links in buffer 0.  On return the
 // current links (FP64) or accumulated transformation (FP32, acc_G) are those
 // after n = st.n sweeps and `st` holds the final state.
+// prepared: the status reset and the first divergence with its stopping test
+// were enqueued by the caller (the mixed hand-over fuses them).
 template <class T>
 int run_phase(lgf_ctx *c, double alpha, double tol, int max_iter, int hist_base, dev_status &st,
-              int stall = 0) {
+              int stall = 0, bool prepared = false) {
     using P = prec<T>;
-    HIPCHK(c, launch_status_reset(c->status, hist_base, c->stream));
-    HIPCHK(c, launch_div_reduce<T>(c->g, P::links(c, 0), P::field(c, 0), c->partials, c->status,
-                                   finp(c, true, tol, max_iter, 0, stall), c->stream));
+    if (!prepared) {
+        HIPCHK(c, launch_status_reset(c->status, hist_base, c->stream));
+        HIPCHK(c, launch_div_reduce<T>(c->g, P::links(c, 0), P::field(c, 0), c->partials,
+                                       c->status, finp(c, true, tol, max_iter, 0, stall),
+                                       c->stream));
+    }
     int rc = read_status(c, st);
     if (rc) return rc;
     const T half_alpha = (T)(0.5 * alpha);
@@ -610,10 +615,20 @@ static int solve(lgf_ctx *c, double *U, double alpha, double tol, int max_iter, 
         if (rc) return rc;
         n32 = st.n;
         code = st.code;
-        // hand-over: U = G U0 G^dagger in FP64 (G reunitarised in FP64)
-        HIPCHK(c, launch_switch(c->g, acc_G(c, n32), U, c->L64[0], c->stream));
-        if (code == ST_CONVERGED || code == ST_MAXITER || code == ST_STALLED) {
-            rc = run_phase<double>(c, alpha, tol, max_iter - n32, n32, st);
+        // hand-over: U = G U0 G^dagger in FP64 (G reunitarised in FP64); for
+        // SU(3) fused with the FP64 phase's first divergence
+        const bool refine = code == ST_CONVERGED || code == ST_MAXITER || code == ST_STALLED;
+        const bool fused = refine && c->g.nc == 3;
+        if (fused) {
+            HIPCHK(c, launch_status_reset(c->status, n32, c->stream));
+            HIPCHK(c, launch_switch_div(c->g, acc_G(c, n32), U, c->L64[0], c->D64[0], c->partials,
+                                        c->status, finp(c, true, tol, max_iter - n32, 0, 0),
+                                        c->stream));
+        } else {
+            HIPCHK(c, launch_switch(c->g, acc_G(c, n32), U, c->L64[0], c->stream));
+        }
+        if (refine) {
+            rc = run_phase<double>(c, alpha, tol, max_iter - n32, n32, st, 0, fused);
             if (rc) return rc;
             n64 = st.n;
             code = st.code;

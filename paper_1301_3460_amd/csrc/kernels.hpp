@@ -137,6 +137,11 @@ hipError_t launch_reduce_only(const double *partials, int nparts, double *out2, 
 hipError_t launch_g_identity(void *G32, const geom &g, hipStream_t st);
 hipError_t launch_switch(const geom &g, const void *G32, const double *U0aos, void *L64,
                          hipStream_t st);
+// launch_switch (SU(3)) fused with launch_div_reduce<double> of its links:
+// the same links, field, partials and stopping test
+hipError_t launch_switch_div(const geom &g, const void *G32, const double *U0aos, void *L64,
+                             void *D, double *partials, dev_status *status, const fin_params &fp,
+                             hipStream_t st);
 
 hipError_t launch_field_from_matrix(const double *Maos, void *D64, long V, long S, hipStream_t st);
 hipError_t launch_matrix_from_field(const void *D64, double *Maos, long V, long S, hipStream_t st);

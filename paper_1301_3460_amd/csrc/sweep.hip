@@ -409,6 +409,54 @@ __global__ void __launch_bounds__(SITE_BLOCK)
     }
 }
 
+// The hand-over fused with the first FP64 divergence: the links of x as in
+// k_switch (stored), the links U_mu(x-mu) formed again from G(x-mu), U0 and
+// G(x) exactly as their own site forms them, then Delta(x) and the block
+// partials of F and theta, as k_div_reduce would compute them from the stored
+// links (the same values in the same order).
+template <int NR, class TF>
+__global__ void __launch_bounds__(SITE_BLOCK)
+    k_switch_div(geom g, const float2 *__restrict__ G, const double2 *__restrict__ U0,
+                 double2 *__restrict__ L, vec2_t<TF> *__restrict__ D, double *__restrict__ partials) {
+    const long s = block_site(g, blockIdx.x, gridDim.x, threadIdx.x);
+    double fs = 0, ts = 0;
+    if (s < g.V) {
+        const nbr n = neighbours(g, s);
+        const mat3<double> g0 = load_G_fp64(G, g.S, s);
+        xacc<double> X;
+        xacc_zero(X);
+        double tr = 0;
+        auto aos = [&](int mu, long x) {
+            mat3<double> u;
+            const double2 *p = U0 + ((long)mu * g.V + x) * 9;
+#pragma unroll
+            for (int k = 0; k < 3 * NR; ++k) u.e[k / 3][k % 3] = mk<double>(p[k].x, p[k].y);
+            if constexpr (NR == 2) rebuild_row2(u);
+            return u;
+        };
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const mat3<double> un = mul_abcd<NR>(g0, aos(mu, s), load_G_fp64(G, g.S, n.p[mu]));
+            store_link<double, NR>(L, g.S, mu, s, un);
+            mat3<double> u = un;
+            if constexpr (NR == 2) rebuild_row2(u);  // as loaded back from 12 reals
+            tr += retrace(u);
+            xacc_add(X, u, -1.0);
+            mat3<double> um = mul_abcd<NR>(load_G_fp64(G, g.S, n.m[mu]), aos(mu, n.m[mu]), g0);
+            if constexpr (NR == 2) rebuild_row2(um);
+            xacc_add(X, um, 1.0);
+        }
+        cpx<double> f0, f1, f2, f3;
+        ts = delta_pack(X, f0, f1, f2, f3);
+        fs = tr;
+        st<TF>(D + s, cvt<TF>(f0));
+        st<TF>(D + g.S + s, cvt<TF>(f1));
+        st<TF>(D + 2 * g.S + s, cvt<TF>(f2));
+        st<TF>(D + 3 * g.S + s, cvt<TF>(f3));
+    }
+    block_sum2<SITE_BLOCK>(fs, ts, partials, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // gauge-invariant checks and F_U[g]
 // ---------------------------------------------------------------------------
@@ -924,6 +972,27 @@ hipError_t launch_switch(const geom &g, const void *G32, const double *U0aos, vo
     auto Lp = static_cast<double2 *>(L64);
     if (g.nr == 3) k_switch<3><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp);
     else k_switch<2><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp);
+    return hipGetLastError();
+}
+
+hipError_t launch_switch_div(const geom &g, const void *G32, const double *U0aos, void *L64,
+                             void *D, double *partials, dev_status *status, const fin_params &fp,
+                             hipStream_t st) {
+    if (g.nc != 3) return hipErrorInvalidValue;
+    const hipError_t e = with_field_type<double>(g, [&](auto tf) -> hipError_t {
+        using TF = decltype(tf);
+        auto Gp = static_cast<const float2 *>(G32);
+        auto U0 = reinterpret_cast<const double2 *>(U0aos);
+        auto Lp = static_cast<double2 *>(L64);
+        auto Dp = static_cast<vec2_t<TF> *>(D);
+        if (g.nr == 3)
+            k_switch_div<3, TF><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp, Dp, partials);
+        else
+            k_switch_div<2, TF><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp, Dp, partials);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    if (fp.enabled) k_finalize<<<1, FIN_BLOCK, 0, st>>>(partials, site_blocks(g.V), status, fp);
     return hipGetLastError();
 }
 

@@ -4,6 +4,12 @@ One step = one Fourier-accelerated steepest-descent sweep of the whole
 lattice (FFT of the divergence, momentum-space scaling, inverse FFT, gauge
 transformation, link update, next divergence, F/theta reductions), FP64.
 
+The headline is the steady-state sweep rate: every lgf_iterate call also packs
+the caller's links, computes the first divergence and unpacks the result, so
+the bench times iterate(K) and iterate(2K) (medians over repeats, each run
+bracketed by device synchronisations) and divides the difference by K; the
+per-call costs are reported beside it.
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--solves R]
@@ -26,6 +32,7 @@ TOL = 1e-15
 L = (32, 32, 32, 32)
 EPS_ALL = (0.6, 0.45, 0.35)
 EPS_MAIN = 0.45
+REPS = 5  # repeats per timed iterate() length (medians)
 BYTES_UPDATE_18 = 4 * 144 * 2 + 128  # update with 18-real links: R+W 4 x 144 B, R+W 64 B
 BYTES_UPDATE_SU2 = 4 * 32 * 2 + 32 * 2  # SU(2) update: R+W 4 links x 32 B, R+W 2 fields
 SD_TOL = 1e-10  # plain steepest descent needs thousands of sweeps at 32^4
@@ -40,7 +47,12 @@ BYTES_PER_SITE = {
     "fp32": {"fft_xy_fwd": 64, "fft_zt": 64, "fft_xy_inv": 128, "update": 272, "finalize": 0},
 }
 BYTES_XY_INV_ACC_SEPARATE = 64 + 32 + 96
-
+# differentiation kernels, algorithmic bytes per site: dF/domega reads the
+# divergence of the rotated links (64) and omega (64) and writes the gradient
+# (64); dtheta/deps reads the 12-real links (384), Delta (64; neighbours
+# reused), eps (4 x 64) and writes the gradient (4 x 64)
+BYTES_OMEGA_GRAD = 3 * 64
+BYTES_THETA_GRAD = 384 + 64 + 256 + 256
 
 # sources that determine the update kernel's code (for the traffic record)
 UPDATE_SOURCES = ("paper_1301_3460_amd/csrc/sweep.hip", "paper_1301_3460_amd/csrc/common.hpp",
@@ -74,6 +86,64 @@ def measured_traffic():
     return rec["read_bytes"] + rec["write_bytes"]
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (the "Model name" lscpu prints)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def timed(fn, reps, setup=None):
+    """Median wall time of fn() over reps runs, each bracketed by device
+    synchronisations (setup(), untimed, runs before each); returns
+    (seconds, result of the last run)."""
+    import numpy as np
+    import torch
+
+    ts, r = [], None
+    for _ in range(reps):
+        if setup is not None:
+            setup()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), r
+
+
+def steady_sweeps(ctx, U0, work, K, reps=REPS):
+    """Steady-state seconds per sweep, (t(2K) - t(K)) / K with t(n) the median
+    time of one iterate(n) call, and the per-call cost t(0) (pack, first
+    divergence, unpack, status reads).  Every run must apply exactly the n
+    sweeps asked for (a fixed count has no stopping test)."""
+
+    def run(n):
+        def call():
+            r = ctx.iterate(work, ALPHA, n)
+            if r.iterations != n:
+                raise RuntimeError(f"iterate({n}) applied {r.iterations} sweeps "
+                                   f"(status {r.status})")
+            return r
+
+        return timed(call, reps, setup=lambda: work.copy_(U0))
+
+    t1, _ = run(K)
+    t2, r2 = run(2 * K)
+    t0, _ = run(0)
+    return {"s_per_sweep": (t2 - t1) / K, "t_K": t1, "t_2K": t2, "t_0": t0, "last": r2}
+
+
+def solve_timing(ctx, U, work, reps, max_iter=2000):
+    t, res = timed(lambda: ctx.fix(work, ALPHA, TOL, max_iter), reps, setup=lambda: work.copy_(U))
+    return t, res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +152,8 @@ def main() -> int:
     ap.add_argument("--solves", type=int, default=5, help="repeats per time-to-theta solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=12)
+    ap.add_argument("--no-cpu-solve", action="store_true",
+                    help="skip the oracle's full 32^4 solve in the CPU baseline")
     ap.add_argument("--lattice", choices=("32^4", "48^3x96"), default="32^4",
                     help="with --sweeps-only: the lattice whose sweeps are timed and profiled")
     ap.add_argument("--no-large", action="store_true",
@@ -89,6 +161,8 @@ def main() -> int:
     ap.add_argument("--sweeps-only", action="store_true",
                     help="only the timed sweeps, the per-kernel timing and one device copy of "
                          "the 32^4 link field (a known-size reference for HBM counters)")
+    ap.add_argument("--autograd-only", action="store_true",
+                    help="only the forward+backward timing of the differentiable forms")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -103,6 +177,11 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     lgf.load()
+
+    if args.autograd_only:
+        print(json.dumps({"autograd": autograd_variant(lgf, inputs, torch, np)}), flush=True)
+        return 0
+
     Lrun, lat_key = (L, "32^4")
     if args.lattice != "32^4":
         if not args.sweeps_only:
@@ -147,17 +226,18 @@ def main() -> int:
     ctx64 = lgf.Context(Lrun, "fp64")
     ctx32 = lgf.Context(Lrun, "mixed")
 
-    # ---- sweep throughput (the headline value): K sweeps after W warmup sweeps
+    # ---- sweep throughput (the headline value), after W warmup sweeps
     work.copy_(U0)
     ctx64.iterate(work, ALPHA, args.warmup)
-    work.copy_(U0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r = ctx64.iterate(work, ALPHA, args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ips = args.steps / dt
-    log(f"FP64 sweeps: {args.steps} in {dt * 1e3:.2f} ms -> {ips:.1f} sweeps/s (F={r.F:.12f})")
+    ss = steady_sweeps(ctx64, U0, work, args.steps)
+    dt_sweep = ss["s_per_sweep"]
+    ips = 1.0 / dt_sweep
+    overhead = {"per_call_ms": round(1e3 * ss["t_0"], 4),
+                "iterate_K_ms": round(1e3 * ss["t_K"], 4),
+                "iterate_2K_ms": round(1e3 * ss["t_2K"], 4),
+                "single_call_rate": round(args.steps / ss["t_K"], 2)}
+    log(f"FP64 sweeps: {1e6 * dt_sweep:.2f} us/sweep -> {ips:.1f} sweeps/s steady state; "
+        f"per-call {overhead}")
 
     # ---- per-kernel durations (HIP events on the library stream)
     prof64 = ctx64.profile(U0, ALPHA, 50)
@@ -183,7 +263,8 @@ def main() -> int:
         torch.cuda.synchronize()
         log(f"reference copy: {U0.numel() * 16} bytes read and written")
         print(json.dumps({"value": round(ips, 2), "unit": "iters/s", "per_kernel": per_kernel,
-                          "roofline_update_GBps": round(achieved, 1),
+                          "overhead": overhead, "roofline_update_GBps": round(achieved, 1),
+                          "sweep_GBps": round(1280 * V * ips / 1e9, 1),
                           "copy_bytes": U0.numel() * 16}), flush=True)
         return 0
 
@@ -191,15 +272,8 @@ def main() -> int:
     solves = {}
     for eps in EPS_ALL:
         for prec, ctx in (("fp64", ctx64), ("mixed", ctx32)):
-            times, res = [], None
-            for _ in range(args.solves):
-                work.copy_(configs[eps])
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                res = ctx.fix(work, ALPHA, TOL, 2000)
-                torch.cuda.synchronize()
-                times.append(time.perf_counter() - t0)
-            entry = {"ms": round(1e3 * float(np.median(times)), 3), "iterations": res.iterations,
+            t, res = solve_timing(ctx, configs[eps], work, args.solves)
+            entry = {"ms": round(1e3 * t, 3), "iterations": res.iterations,
                      "fp32_iterations": res.fp32_iterations, "status": res.status,
                      "F": res.F, "theta": res.theta}
             if eps in golden:
@@ -216,15 +290,8 @@ def main() -> int:
     variants = {}
     for prec, ctx in (("fp64", ctx64), ("mixed", ctx32)):
         ctx.set_exponential(True)
-        times = []
-        for _ in range(args.solves):
-            work.copy_(U0)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            res = ctx.fix(work, ALPHA, TOL, 2000)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-        entry = {"ms": round(1e3 * float(np.median(times)), 3), "iterations": res.iterations,
+        t, res = solve_timing(ctx, U0, work, args.solves)
+        entry = {"ms": round(1e3 * t, 3), "iterations": res.iterations,
                  "fp32_iterations": res.fp32_iterations, "status": res.status, "F": res.F,
                  "theta": res.theta}
         if golden_exp:
@@ -238,15 +305,8 @@ def main() -> int:
     # later hand-over points of the mixed solve (FP32 sweeps further down)
     for sw in (1e-9, 1e-10, 1e-11):
         ctx32.set_theta_switch(sw)
-        times = []
-        for _ in range(args.solves):
-            work.copy_(U0)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            res = ctx32.fix(work, ALPHA, TOL, 2000)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-        e = {"ms": round(1e3 * float(np.median(times)), 3), "iterations": res.iterations,
+        t, res = solve_timing(ctx32, U0, work, args.solves)
+        e = {"ms": round(1e3 * t, 3), "iterations": res.iterations,
              "fp32_iterations": res.fp32_iterations, "status": res.status, "F": res.F,
              "theta": res.theta}
         if golden:
@@ -258,42 +318,21 @@ def main() -> int:
     # FP64 sweeps with the Fourier field held in FP32
     ctx64.set_field_precision(32)
     ctx32.set_field_precision(32)
-    work.copy_(U0)
-    ctx64.iterate(work, ALPHA, args.warmup)
-    work.copy_(U0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx64.iterate(work, ALPHA, args.steps)
-    torch.cuda.synchronize()
-    ipsf = args.steps / (time.perf_counter() - t0)
+    ssf = steady_sweeps(ctx64, U0, work, args.steps)
     proff = ctx64.profile(U0, ALPHA, 20)
-    e = {"sweeps_per_s": round(ipsf, 1), "per_kernel_ms": {k: round(v, 5) for k, v in proff.items()},
-         "bytes_per_site": 1024}
+    e = {"sweeps_per_s": round(1.0 / ssf["s_per_sweep"], 1),
+         "per_kernel_ms": {k: round(v, 5) for k, v in proff.items()}, "bytes_per_site": 1024}
     for prec, ctx in (("fp64", ctx64), ("mixed", ctx32)):
-        times = []
-        for _ in range(args.solves):
-            work.copy_(U0)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            res = ctx.fix(work, ALPHA, TOL, 2000)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-        e[f"solve_ms_{prec}"] = round(1e3 * float(np.median(times)), 3)
+        t, res = solve_timing(ctx, U0, work, args.solves)
+        e[f"solve_ms_{prec}"] = round(1e3 * t, 3)
         e[f"iterations_{prec}"] = res.iterations
         if golden:
             e[f"dF_vs_oracle_{prec}"] = abs(res.F - golden[EPS_MAIN]["F"])
     # the fastest combination: mixed, FP32 field, hand-over at 1e-11
     ctx32.set_theta_switch(1e-11)
-    times = []
-    for _ in range(args.solves):
-        work.copy_(U0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = ctx32.fix(work, ALPHA, TOL, 2000)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
+    t, res = solve_timing(ctx32, U0, work, args.solves)
     ctx32.set_theta_switch(1e-8)
-    e["solve_ms_mixed_switch_1e-11"] = round(1e3 * float(np.median(times)), 3)
+    e["solve_ms_mixed_switch_1e-11"] = round(1e3 * t, 3)
     if golden:
         e["dF_vs_oracle_mixed_switch_1e-11"] = abs(res.F - golden[EPS_MAIN]["F"])
     ctx64.set_field_precision(64)
@@ -303,29 +342,15 @@ def main() -> int:
 
     # 18-real working links (all three rows stored) against the 12-real default
     ctx64.set_link_format(18)
-    work.copy_(U0)
-    ctx64.iterate(work, ALPHA, args.warmup)
-    work.copy_(U0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx64.iterate(work, ALPHA, args.steps)
-    torch.cuda.synchronize()
-    ips18 = args.steps / (time.perf_counter() - t0)
+    ss18 = steady_sweeps(ctx64, U0, work, args.steps)
     upd18 = ctx64.profile(U0, ALPHA, 20)["update"]
-    times = []
-    for _ in range(args.solves):
-        work.copy_(U0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = ctx64.fix(work, ALPHA, TOL, 2000)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
+    t, res = solve_timing(ctx64, U0, work, args.solves)
     ctx64.set_link_format(12)
     variants["link18/fp64"] = {
-        "sweeps_per_s": round(ips18, 1), "update_ms": round(upd18, 5),
+        "sweeps_per_s": round(1.0 / ss18["s_per_sweep"], 1), "update_ms": round(upd18, 5),
         "update_GBps": round(BYTES_UPDATE_18 * V / (upd18 * 1e-3) / 1e9, 1),
         "update_bytes_per_site": BYTES_UPDATE_18,
-        "solve_ms": round(1e3 * float(np.median(times)), 3), "iterations": res.iterations,
+        "solve_ms": round(1e3 * t, 3), "iterations": res.iterations,
         "F": res.F, "dF_vs_oracle": abs(res.F - golden[EPS_MAIN]["F"]) if golden else None}
     log(f"18-real links: {variants['link18/fp64']}")
     # SU(2) on the same lattice (N_c = 2; links stored as row 0)
@@ -335,26 +360,14 @@ def main() -> int:
     c2 = lgf.Context(L, "fp64", nc=2)
     w2.copy_(U2)
     c2.iterate(w2, ALPHA, args.warmup)
-    w2.copy_(U2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    c2.iterate(w2, ALPHA, args.steps)
-    torch.cuda.synchronize()
-    ips2 = args.steps / (time.perf_counter() - t0)
+    ss2 = steady_sweeps(c2, U2, w2, args.steps)
     prof2 = c2.profile(U2, ALPHA, 20)
-    times = []
-    for _ in range(args.solves):
-        w2.copy_(U2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = c2.fix(w2, ALPHA, TOL, 2000)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    entry = {"sweeps_per_s": round(ips2, 1),
+    t, res = solve_timing(c2, U2, w2, args.solves)
+    entry = {"sweeps_per_s": round(1.0 / ss2["s_per_sweep"], 1),
              "per_kernel_ms": {k: round(v, 5) for k, v in prof2.items()},
              "update_GBps": round(BYTES_UPDATE_SU2 * V / (prof2["update"] * 1e-3) / 1e9, 1),
              "update_bytes_per_site": BYTES_UPDATE_SU2,
-             "solve_ms": round(1e3 * float(np.median(times)), 3), "iterations": res.iterations,
+             "solve_ms": round(1e3 * t, 3), "iterations": res.iterations,
              "status": res.status, "F": res.F}
     if golden_su2:
         entry["dF_vs_oracle"] = abs(res.F - golden_su2["F"])
@@ -363,15 +376,8 @@ def main() -> int:
     log(f"SU(2): {entry}")
     c2.close()
     c2m = lgf.Context(L, "mixed", nc=2)
-    times = []
-    for _ in range(args.solves):
-        w2.copy_(U2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = c2m.fix(w2, ALPHA, TOL, 2000)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    entry = {"solve_ms": round(1e3 * float(np.median(times)), 3), "iterations": res.iterations,
+    t, res = solve_timing(c2m, U2, w2, args.solves)
+    entry = {"solve_ms": round(1e3 * t, 3), "iterations": res.iterations,
              "fp32_iterations": res.fp32_iterations, "status": res.status, "F": res.F}
     if golden_su2:
         entry["dF_vs_oracle"] = abs(res.F - golden_su2["F"])
@@ -393,20 +399,16 @@ def main() -> int:
         c48 = lgf.Context(L48, "fp64")
         w48.copy_(U48)
         c48.iterate(w48, ALPHA, 3)
-        w48.copy_(U48)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        n48 = 100
-        c48.iterate(w48, ALPHA, n48)
-        torch.cuda.synchronize()
-        ips48 = n48 / (time.perf_counter() - t0)
+        ss48 = steady_sweeps(c48, U48, w48, 20, reps=3)
+        ips48 = 1.0 / ss48["s_per_sweep"]
         prof48 = c48.profile(U48, ALPHA, 5)
         variants["48^3x96/fp64"] = {
             "sweeps_per_s": round(ips48, 2),
             "per_kernel_ms": {k: round(v, 4) for k, v in prof48.items()},
             "update_GBps": round(BYTES_PER_SITE["fp64"]["update"] * V48 /
                                  (prof48["update"] * 1e-3) / 1e9, 1),
-            "sweep_GBps": round(1280 * V48 * ips48 / 1e9, 1)}
+            "sweep_GBps": round(1280 * V48 * ips48 / 1e9, 1),
+            "per_call_ms": round(1e3 * ss48["t_0"], 3)}
         log(f"48^3x96: {variants['48^3x96/fp64']}")
         g48 = None
         gpath = os.path.join(ROOT, "tests", "golden", "oracle_483x96.json")
@@ -415,12 +417,8 @@ def main() -> int:
                 g48 = json.load(f)["runs"][0]
         c48m = lgf.Context(L48, "mixed")
         for prec, ctx in (("fp64", c48), ("mixed", c48m)):
-            w48.copy_(U48)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            res = ctx.fix(w48, ALPHA, TOL, 2000)
-            torch.cuda.synchronize()
-            entry = {"ms": round(1e3 * (time.perf_counter() - t0), 3),
+            t, res = solve_timing(ctx, U48, w48, 1)
+            entry = {"ms": round(1e3 * t, 3),
                      "iterations": res.iterations, "fp32_iterations": res.fp32_iterations,
                      "status": res.status, "F": res.F, "theta": res.theta}
             if g48:
@@ -434,34 +432,45 @@ def main() -> int:
         torch.cuda.empty_cache()
 
     ctx64.set_acceleration(False)
-    work.copy_(U0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = ctx64.fix(work, ALPHA, SD_TOL, 20000)
-    torch.cuda.synchronize()
-    sd_s = time.perf_counter() - t0
+    t, res = timed(lambda: ctx64.fix(work, ALPHA, SD_TOL, 20000), 1,
+                   setup=lambda: work.copy_(U0))
     ctx64.set_acceleration(True)
-    variants["plain_sd/fp64"] = {"theta_tol": SD_TOL, "ms": round(1e3 * sd_s, 3),
+    variants["plain_sd/fp64"] = {"theta_tol": SD_TOL, "ms": round(1e3 * t, 3),
                                  "iterations": res.iterations, "status": res.status,
-                                 "sweeps_per_s": round(res.iterations / sd_s, 1),
+                                 "sweeps_per_s": round(res.iterations / t, 1),
                                  "accelerated_iterations_same_tol": golden_iters_at(SD_TOL)}
     log(f"plain steepest descent: {variants['plain_sd/fp64']}")
 
-    # ---- CPU baseline: the oracle on this host, bounded sample
+    # differentiation (forward + backward of the autograd functions)
+    variants["autograd"] = autograd_variant(lgf, inputs, torch, np)
+
+    # ---- CPU baseline: the oracle on this host's cores
     cpu = None
     if not args.no_cpu:
         import oracle
 
+        threads = len(os.sched_getaffinity(0))
+        oracle.set_threads(threads)
         Uh = configs[EPS_MAIN].cpu().numpy()
         n = args.cpu_sweeps
         t0 = time.perf_counter()
         oracle.iterate(Uh, ALPHA, n)
         cdt = time.perf_counter() - t0
         cpu = {"value": round(n / cdt, 4), "unit": "iters/s", "cores": oracle.get_threads(),
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"{n} FP64 sweeps of the 32^4 eps={EPS_MAIN} configuration "
-                         f"({cdt:.1f} s, plain C/OpenMP oracle)"}
-        log(f"cpu oracle: {cpu}")
+                         f"({cdt:.1f} s, plain C/OpenMP oracle, "
+                         f"{oracle.get_threads()} threads = the process's CPU affinity)"}
+        log(f"cpu oracle sweeps: {cpu}")
+        if not args.no_cpu_solve:
+            t0 = time.perf_counter()
+            ref = oracle.fix(Uh, ALPHA, TOL, 2000)
+            cs = time.perf_counter() - t0
+            cpu["time_to_theta_s"] = round(cs, 3)
+            cpu["time_to_theta_iterations"] = ref["iterations"]
+            cpu["time_to_theta_F"] = ref["F"]
+            cpu["gpu_speedup_time_to_theta_fp64"] = round(1e3 * cs / t64, 1)
+            log(f"cpu oracle solve: {cs:.1f} s, {ref['iterations']} sweeps")
 
     out = {
         "metric": METRIC,
@@ -470,7 +479,7 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * dt / args.steps, 5),
+        "ms_per_step": round(1e3 * dt_sweep, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -479,11 +488,15 @@ def main() -> int:
         "config": {"workload": "SU(3) 32^4, FP64 Fourier-accelerated steepest descent, "
                                f"alpha={ALPHA}, eps={EPS_MAIN} links + Haar gauge transformation",
                    "lattice": list(L), "sites": V},
+        "timing": "steady state: (t(iterate 2K) - t(iterate K)) / K, medians of "
+                  f"{REPS} runs each; per-call costs in 'overhead'",
+        "overhead": overhead,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(),
                      "kernel": "k_update<double> (update + next divergence)",
                      "bytes_per_site": BYTES_PER_SITE["fp64"]["update"]},
+        "sweep_roofline_frac": round(1280 * V * ips / 1e9 / HBM_PEAK_GBS, 4),
         "cpu_baseline": cpu,
         "time_to_theta_ms": {"fp64": t64, "mixed": tmx, "speedup_mixed": round(t64 / tmx, 3)},
         "solves": solves,
@@ -492,6 +505,60 @@ def main() -> int:
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def autograd_variant(lgf, inputs, torch, np):
+    """Forward and forward+backward rates of LandauF (dF/domega) and
+    LandauTheta (dtheta/deps) on the differentiation workloads (4^4 and 16^4,
+    eps = 0.5 links + Haar gauge transformation) and on 32^4."""
+    out = {}
+    for key, L, seed, reps in (("4^4", (4, 4, 4, 4), inputs.CONFIG_SEEDS[("4^4", 0.5)], 50),
+                               ("16^4", (16, 16, 16, 16), inputs.CONFIG_SEEDS[("16^4", 0.5)], 20),
+                               ("32^4", (32, 32, 32, 32), 3205, 10)):
+        V = int(np.prod(L))
+        U = torch.from_numpy(inputs.make_config(L, 0.5, seed)[0]).to("cuda")
+        om0 = torch.from_numpy(inputs.random_omega(L, 0.3, seed + 1)).to("cuda")
+        om = om0.clone().requires_grad_(True)
+        eps = torch.zeros((4,) + inputs.site_shape(L) + (8,), dtype=torch.float64,
+                          device="cuda", requires_grad=True)
+
+        def fwd_F():
+            with torch.no_grad():
+                return lgf.LandauF.apply(om, U)
+
+        def fwdbwd_F():
+            om.grad = None
+            F = lgf.LandauF.apply(om, U)
+            F.backward()
+            return F
+
+        def fwd_T():
+            with torch.no_grad():
+                return lgf.LandauTheta.apply(eps, U)
+
+        def fwdbwd_T():
+            eps.grad = None
+            th = lgf.LandauTheta.apply(eps, U)
+            th.backward()
+            return th
+
+        fwdbwd_F()
+        fwdbwd_T()
+        tF, _ = timed(fwd_F, reps)
+        tFB, _ = timed(fwdbwd_F, reps)
+        tT, _ = timed(fwd_T, reps)
+        tTB, _ = timed(fwdbwd_T, reps)
+        out[key] = {"sites": V,
+                    "F_forward_ms": round(1e3 * tF, 4), "F_fwd_bwd_ms": round(1e3 * tFB, 4),
+                    "F_fwd_bwd_per_s": round(1.0 / tFB, 1),
+                    "theta_forward_ms": round(1e3 * tT, 4),
+                    "theta_fwd_bwd_ms": round(1e3 * tTB, 4),
+                    "theta_fwd_bwd_per_s": round(1.0 / tTB, 1),
+                    "omega_grad_bytes_per_site": BYTES_OMEGA_GRAD,
+                    "theta_grad_bytes_per_site": BYTES_THETA_GRAD}
+        log(f"autograd {key}: {out[key]}")
+        del U, om, om0, eps
+    return out
 
 
 if __name__ == "__main__":

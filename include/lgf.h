@@ -82,8 +82,15 @@ typedef struct {
 } lgf_result;
 
 /* Create a context for lattice L (see conventions) and precision mode.
+ * The lattice is the periodic 4D lattice of V = Lx Ly Lz Lt sites on which
+ * the paper's display equation defines F_U[g]; its comparison runs use 32^4.
+ * precision: LGF_FP64 (the paper's double precision) or LGF_MIXED.
  * stream: a hipStream_t to enqueue on (NULL: the null stream).  The current
- * HIP device at creation is the context's device.  *out receives the context. */
+ * HIP device at creation is the context's device.  *out receives the context
+ * (NULL on failure).  Allocates the context's device scratch (about 1 GiB at
+ * 32^4 FP64).  LGF_ERR_ARG for a NULL pointer, an unsupported extent or
+ * precision; LGF_ERR_OOM if the scratch does not fit; LGF_ERR_DEVICE if no
+ * HIP device is current.  lgf_last_error(NULL) explains a failure. */
 int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream);
 
 /* As lgf_create for the gauge group SU(nc), nc = 3 or 2 (the paper's
@@ -139,23 +146,41 @@ int lgf_set_field_precision(lgf_ctx *ctx, int bits);
  * report). */
 int lgf_set_link_format(lgf_ctx *ctx, int nreal);
 
-/* Exactly n_iter Fourier-accelerated updates of the links U (in place), with
- * no stopping test (n_iter >= 0).  res (may be NULL) gets F and theta of the
- * returned links.  LGF_FP64 only semantics: a LGF_MIXED context runs the
- * sweeps in FP32 and accumulates the transformation, applying it to U in
- * FP64 at the end. */
+/* Exactly n_iter updates of the links U (in place), n_iter >= 0.  One update
+ * is one steepest-descent step with Fourier acceleration (the paragraph
+ * following the display equation; plain steepest descent after
+ * lgf_set_acceleration(ctx, 0)), with the step size alpha > 0 (the paper's
+ * runs use alpha = 0.08).  There is no stopping test: neither theta < tol nor
+ * a rising or stalling theta ends the run.  Only a non-finite theta or F
+ * stops it early, with LGF_ERR_NONFINITE and res->iterations < n_iter.  res
+ * (may be NULL) gets the updates applied and F and theta of the returned
+ * links.  An LGF_MIXED context runs the sweeps in FP32, accumulating the
+ * applied transformation, and applies it to U in FP64 at the end. */
 int lgf_iterate(lgf_ctx *ctx, double *U, double alpha, int n_iter, lgf_result *res);
 
-/* Gauge fixing: updates U in place until theta < theta_tol (tested before
- * each update, so an already-fixed input takes 0 updates) or max_iter
- * updates.  alpha > 0, theta_tol > 0, max_iter >= 0. */
+/* Gauge fixing by Fourier-accelerated steepest descent (the paragraph
+ * following the display equation), with the parameters of the paper's
+ * comparison runs (alpha = 0.08, stopping criterion theta < 1e-15; the
+ * paragraph on those runs).  Updates U in place until theta < theta_tol
+ * (tested before each update, so an already-fixed input takes 0 updates) or
+ * max_iter updates.  alpha > 0, theta_tol > 0, max_iter >= 0, else
+ * LGF_ERR_ARG with U untouched.  Returns LGF_OK (converged),
+ * LGF_NOT_CONVERGED (max_iter reached), LGF_ERR_NONFINITE or LGF_DIVERGING
+ * (theta rose for 8 sweeps in a row to over 100x its minimum, e.g. for alpha
+ * above 2/p2max); these still fill res and write back the last iterate.
+ * LGF_MIXED: FP32 sweeps until theta < the hand-over threshold
+ * (lgf_set_theta_switch), then FP64 sweeps to theta_tol. */
 int lgf_fix(lgf_ctx *ctx, double *U, double alpha, double theta_tol, int max_iter,
             lgf_result *res);
 
 /* F_U[g] of the display equation (g == NULL: identity) into *F (host). */
 int lgf_functional(lgf_ctx *ctx, const double *U, const double *g, double *F);
 
-/* theta of the links U into *theta (host). */
+/* theta of the links U into *theta (host): the quantity the paper's
+ * comparison runs bring below 1e-15.  The paper does not print its formula;
+ * this is the reading theta = 1/(Nc V) sum_x Tr[Delta(x) Delta(x)^dagger] with
+ * Delta as above (no factor 1/2), equal to 384 V |dF/domega|^2 at omega = 0.
+ * Synchronises the context's stream. */
 int lgf_theta(lgf_ctx *ctx, const double *U, double *theta);
 
 /* Average plaquette 1/(6 Nc V) sum_x sum_{mu<nu} Re Tr U_mu(x) U_nu(x+mu)

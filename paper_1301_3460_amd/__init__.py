@@ -435,31 +435,41 @@ def _autograd_functions():
     import torch
 
     class LandauF(torch.autograd.Function):
-        """F_U[exp(i omega.T)] with a hand-written backward (dF/domega)."""
+        """F_U[exp(i omega.T)] with a hand-written backward (dF/domega).
+
+        forward evaluates F only (lgf_functional_omega); backward launches
+        the gradient kernels (lgf_functional_omega_grad), so a forward under
+        torch.no_grad() pays for no gradient."""
 
         @staticmethod
         def forward(ctx, omega, U):
-            F, grad = _ctx(U).functional_omega_grad(U, omega.detach().contiguous())
-            ctx.save_for_backward(grad)
+            om = omega.detach().contiguous()
+            F = _ctx(U).functional_omega(U, om)
+            ctx.save_for_backward(om, U)
             return torch.tensor(F, dtype=torch.float64, device=omega.device)
 
         @staticmethod
         def backward(ctx, gout):
-            (grad,) = ctx.saved_tensors
+            om, U = ctx.saved_tensors
+            _, grad = _ctx(U).functional_omega_grad(U, om)
             return gout * grad, None
 
     class LandauTheta(torch.autograd.Function):
-        """theta of the links exp(i eps.T) U with a hand-written backward."""
+        """theta of the links exp(i eps.T) U with a hand-written backward.
+
+        forward evaluates theta only; backward launches the gradient kernel."""
 
         @staticmethod
         def forward(ctx, eps, U):
-            th, grad = _ctx(U).theta_grad(U, eps.detach().contiguous())
-            ctx.save_for_backward(grad)
+            ep = eps.detach().contiguous()
+            th, _ = _ctx(U).theta_grad(U, ep, need_grad=False)
+            ctx.save_for_backward(ep, U)
             return torch.tensor(th, dtype=torch.float64, device=eps.device)
 
         @staticmethod
         def backward(ctx, gout):
-            (grad,) = ctx.saved_tensors
+            ep, U = ctx.saved_tensors
+            _, grad = _ctx(U).theta_grad(U, ep)
             return gout * grad, None
 
     return LandauF, LandauTheta

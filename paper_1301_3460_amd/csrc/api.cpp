@@ -43,6 +43,7 @@ struct lgf_ctx {
     double theta_switch = 1e-8;
     bool accelerate = true;  // false: plain steepest descent (no transform)
     bool exact_exp = false;  // true: g = exp((alpha/2) L Delta) exactly
+    double half_alpha = 0;   // alpha/2 of the sweeps being enqueued (FP64 G accumulation)
 
     // working links (SoA; 12-real by default, 18-real or SU(2) row 0 by the
     // context's format): FP64 double buffer; the FP32 pair aliases L64[1]
@@ -220,13 +221,13 @@ hipError_t sweep_pass(lgf_ctx *c, int cur, void *D, T half_alpha, int pass) {
         if (c->g.nc == 3 && pass == 2) {
             if (c->accelerate && xy_acc_fusable<float>(c->g))
                 return launch_fft_xy_inv_acc<float>(c->g, D, c->tw32, acc_G(c, cur),
-                                                    acc_G(c, cur ^ 1), half_alpha, c->exact_exp,
+                                                    acc_G(c, cur ^ 1), c->half_alpha, c->exact_exp,
                                                     c->status, c->stream);
             if (c->accelerate) {
                 const hipError_t e = transform_pass(c, true, 2, D);
                 if (e != hipSuccess) return e;
             }
-            return launch_gauge_acc(c->g, D, acc_G(c, cur), acc_G(c, cur ^ 1), half_alpha,
+            return launch_gauge_acc(c->g, D, acc_G(c, cur), acc_G(c, cur ^ 1), c->half_alpha,
                                     c->exact_exp, c->status, c->stream);
         }
     }
@@ -271,6 +272,7 @@ int run_phase(lgf_ctx *c, double alpha, double tol, int max_iter, int hist_base,
     int rc = read_status(c, st);
     if (rc) return rc;
     const T half_alpha = (T)(0.5 * alpha);
+    c->half_alpha = 0.5 * alpha;
     int enq = 0;  // sweeps enqueued so far
     double th_prev = st.theta;
     int n_prev = st.n;
@@ -394,6 +396,7 @@ int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
     std::vector<hipEvent_t> ev((size_t)n * 6);
     for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
     const T half_alpha = (T)(0.5 * alpha);
+    c->half_alpha = 0.5 * alpha;
     int rc = LGF_OK;
     for (int it = 0; it < n && rc == LGF_OK; ++it) {
         const int cur = it & 1;

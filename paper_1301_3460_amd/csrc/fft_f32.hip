@@ -10,7 +10,7 @@ template zt_plan plan_zt<float>(const geom &, size_t);
 template void fft_set_max_lds<float>(const geom &, const zt_plan &);
 template bool xy_acc_fusable<float>(const geom &);
 template hipError_t launch_fft_xy_inv_acc<float>(const geom &, void *, const void *, const void *,
-                                                 void *, float, bool, const dev_status *,
+                                                 void *, double, bool, const dev_status *,
                                                  hipStream_t);
 template hipError_t launch_fft_zt<float>(const geom &, void *, int, const void *, const float *,
                                          float, const zt_plan &, const dev_status *, hipStream_t);

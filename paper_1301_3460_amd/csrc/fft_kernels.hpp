@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(XY_BLOCK)
 template <class T, int RMAX, bool EXACT>
 __global__ void __launch_bounds__(XY_BLOCK)
     k_fft_xy_acc(geom g, const vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
-                 const vec2_t<T> *__restrict__ Gold, vec2_t<T> *__restrict__ Gnew, T c,
+                 const vec2_t<T> *__restrict__ Gold, vec2_t<T> *__restrict__ Gnew, double c,
                  const dev_status *__restrict__ status) {
     if (status->done) return;
     extern __shared__ unsigned char smem_raw[];
@@ -106,25 +106,8 @@ __global__ void __launch_bounds__(XY_BLOCK)
     for (int i = threadIdx.x; i < Lxy; i += XY_BLOCK) {
         const int y = i / Lx, x = i - y * Lx;
         const vec2_t<T> *q = lds + y * P + x;
-        const cpx<T> f0 = ld<T>(q), f1 = ld<T>(q + REG), f2 = ld<T>(q + 2 * REG),
-                     f3 = ld<T>(q + 3 * REG);
-        mat3<T> gx;
-        if constexpr (EXACT) gx = gauge_exp_from_entries<T>(f0, f1, f2, f3, c);
-        else gx = gauge_from_entries<T>(f0, f1, f2, f3, c);
-        const long s = s0 + i;
-        mat3<T> G0;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) G0.e[k / 3][k % 3] = ld<T>(Gold + (long)k * g.S + s);
-        rebuild_row2(G0);
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                cpx<T> acc = cmul(gx.e[r][0], G0.e[0][j]);
-                acc = cmac(acc, gx.e[r][1], G0.e[1][j]);
-                acc = cmac(acc, gx.e[r][2], G0.e[2][j]);
-                st<T>(Gnew + (long)(3 * r + j) * g.S + s, acc);
-            }
+        accumulate_G<EXACT>(ld<T>(q), ld<T>(q + REG), ld<T>(q + 2 * REG), ld<T>(q + 3 * REG), c,
+                            Gold, Gnew, g.S, s0 + i);
     }
 }
 
@@ -316,7 +299,7 @@ __global__ void __launch_bounds__(rc_max_threads<T>())
 template <class T, int NY, bool EXACT>
 __global__ void __launch_bounds__(rc_max_threads<T>())
     k_fft_xy_rc_acc(geom g, const vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
-                    const vec2_t<T> *__restrict__ Gold, vec2_t<T> *__restrict__ Gnew, T c,
+                    const vec2_t<T> *__restrict__ Gold, vec2_t<T> *__restrict__ Gnew, double c,
                     const dev_status *__restrict__ status) {
     if (status->done) return;
     extern __shared__ unsigned char smem_raw[];
@@ -342,25 +325,8 @@ __global__ void __launch_bounds__(rc_max_threads<T>())
     for (int i = threadIdx.x; i < (int)Lxy; i += blockDim.x) {
         const int y = i / Lx, xx = i - y * Lx;
         const vec2_t<T> *q = lds + y * PJ + xx;
-        const cpx<T> f0 = ld<T>(q), f1 = ld<T>(q + SW), f2 = ld<T>(q + 2 * SW),
-                     f3 = ld<T>(q + 3 * SW);
-        mat3<T> gx;
-        if constexpr (EXACT) gx = gauge_exp_from_entries<T>(f0, f1, f2, f3, c);
-        else gx = gauge_from_entries<T>(f0, f1, f2, f3, c);
-        const long s = s0 + i;
-        mat3<T> G0;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) G0.e[k / 3][k % 3] = ld<T>(Gold + (long)k * g.S + s);
-        rebuild_row2(G0);
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                cpx<T> acc = cmul(gx.e[r][0], G0.e[0][j]);
-                acc = cmac(acc, gx.e[r][1], G0.e[1][j]);
-                acc = cmac(acc, gx.e[r][2], G0.e[2][j]);
-                st<T>(Gnew + (long)(3 * r + j) * g.S + s, acc);
-            }
+        accumulate_G<EXACT>(ld<T>(q), ld<T>(q + SW), ld<T>(q + 2 * SW), ld<T>(q + 3 * SW), c, Gold,
+                            Gnew, g.S, s0 + i);
     }
 }
 
@@ -478,7 +444,7 @@ template <class T> inline bool xy_acc_fusable(const geom &g) {
 
 template <class T>
 hipError_t launch_fft_xy_inv_acc(const geom &g, void *D, const void *tw, const void *Gold,
-                                 void *Gnew, T c, bool exact, const dev_status *status,
+                                 void *Gnew, double c, bool exact, const dev_status *status,
                                  hipStream_t st) {
     if (!xy_acc_fusable<T>(g)) return hipErrorInvalidValue;
     auto Dp = static_cast<const vec2_t<T> *>(D);

@@ -109,11 +109,11 @@ struct zt_plan {
 template <class T> bool xy_acc_fusable(const geom &g);
 template <class T>
 hipError_t launch_fft_xy_inv_acc(const geom &g, void *D, const void *tw, const void *Gold,
-                                 void *Gnew, T c, bool exact, const dev_status *status,
+                                 void *Gnew, double c, bool exact, const dev_status *status,
                                  hipStream_t st);
 // G(x) <- g(x) G(x) from the field L Delta as a kernel of its own (FP32 sweeps
 // of an SU(3) mixed solve whose inverse (x,y) pass cannot take it)
-hipError_t launch_gauge_acc(const geom &g, const void *LD, const void *Gold, void *Gnew, float c,
+hipError_t launch_gauge_acc(const geom &g, const void *LD, const void *Gold, void *Gnew, double c,
                             bool exact, const dev_status *status, hipStream_t st);
 template <class T> zt_plan plan_zt(const geom &g, size_t lds_budget);
 template <class T> size_t fft_xy_lds_bytes(const geom &g);

@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 // U_mu(x) <- g(x) U_mu(x) g(x+mu)^dagger, fused with the next Delta (which needs
 // the new U_mu(x-mu) = g(x-mu) U_mu(x-mu) g(x)^dagger) and the F/theta partials.
 // ACC_G (the FP32 phase of a mixed solve): also G(x) <- g(x) G(x), G stored as
-// its row 0 like the links.
+// its row 0 like the links, formed and normalised in FP64.
 template <class T, class TF, bool EXACT, bool ACC_G>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_update_su2(geom g, const vec2_t<T> *__restrict__ Lin, vec2_t<T> *__restrict__ Lout,
@@ -172,9 +172,15 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         ts = (double)delta_su2<T, TF>(p, q, Dout, g.S, s);
         fs = (double)tr;
         if constexpr (ACC_G) {
-            const quat<T> Gn = qmul(g0, quat<T>{ld<T>(G + s), ld<T>(G + g.S + s)});
-            st<T>(G + s, Gn.a);
-            st<T>(G + g.S + s, Gn.b);
+            // g formed, multiplied into G and the product normalised in FP64;
+            // only the stored row of G is rounded to FP32
+            const quat<double> g64 = gauge_su2<double, EXACT>(
+                cvt<double>(ld<TF>(LD + s)), cvt<double>(ld<TF>(LD + g.S + s)), (double)c);
+            const quat<double> Gn = qmul(
+                g64, quat<double>{cvt<double>(ld<T>(G + s)), cvt<double>(ld<T>(G + g.S + s))});
+            const double r = rsqrt_nr(norm2(Gn.a) + norm2(Gn.b));
+            st<T>(G + s, cvt<T>(r * Gn.a));
+            st<T>(G + g.S + s, cvt<T>(r * Gn.b));
         }
     }
     block_sum2<SITE_BLOCK>(fs, ts, partials, blockIdx.x);

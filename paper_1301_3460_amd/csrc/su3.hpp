@@ -269,6 +269,39 @@ LGF_HD mat3<T> gauge_exp_from_entries(cpx<T> f0, cpx<T> f1, cpx<T> f2, cpx<T> f3
     return g;
 }
 
+// One step of the accumulated transformation of the FP32 sweeps of a mixed
+// solve, G(x) <- g(x) G(x), in FP64: g is formed from the FP32 entries of
+// L Delta and made unitary in FP64 (first-order step, Gram-Schmidt) or
+// exponentiated in FP64 (exact step); the product with the stored rows 0,1 of
+// G (row 2 rebuilt) is reunitarised in FP64, so G stays on SU(3) to FP32
+// rounding sweep after sweep; only rows 0,1 of the result are rounded to FP32.
+template <bool EXACT>
+LGF_HD void accumulate_G(cpx<float> f0, cpx<float> f1, cpx<float> f2, cpx<float> f3, double c,
+                         const float2 *__restrict__ Gold, float2 *__restrict__ Gnew, long S,
+                         long s) {
+    const cpx<double> e0 = cvt<double>(f0), e1 = cvt<double>(f1), e2 = cvt<double>(f2),
+                      e3 = cvt<double>(f3);
+    mat3<double> gx;
+    if constexpr (EXACT) gx = gauge_exp_from_entries<double>(e0, e1, e2, e3, c);
+    else gx = gauge_from_entries<double>(e0, e1, e2, e3, c);
+    mat3<double> G0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) G0.e[k / 3][k % 3] = cvt<double>(ld<float>(Gold + (long)k * S + s));
+    rebuild_row2(G0);
+    mat3<double> Gn;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cpx<double> acc = cmul(gx.e[r][0], G0.e[0][j]);
+            acc = cmac(acc, gx.e[r][1], G0.e[1][j]);
+            Gn.e[r][j] = cmac(acc, gx.e[r][2], G0.e[2][j]);
+        }
+    reunitarise(Gn);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) st<float>(Gnew + (long)k * S + s, cvt<float>(Gn.e[k / 3][k % 3]));
+}
+
 // The same from a Fourier field at site s.
 template <class T>
 LGF_HD mat3<T> gauge_from_field(const vec2_t<T> *__restrict__ D, long S, long s, T c) {

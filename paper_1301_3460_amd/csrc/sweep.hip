@@ -162,7 +162,9 @@ __device__ __forceinline__ void finalize_state(double A, double B, dev_status *s
     } else if (st.n >= fp.max_iter) {
         st.done = 1;
         st.code = ST_MAXITER;
-    } else {
+    } else if (fp.tol > 0) {
+        // a solve (tol > 0) also stops when theta diverges or stalls; a fixed
+        // count of sweeps (tol == 0) runs them all
         st.rises = (st.n > 0 && th > st.theta_prev) ? st.rises + 1 : 0;
         st.since_min = (st.n == 0 || th < st.theta_min) ? 0 : st.since_min + 1;
         if (st.rises >= DIVERGE_RISES && th > DIVERGE_GROWTH * st.theta_min) {
@@ -810,31 +812,16 @@ __global__ void __launch_bounds__(256)
 // FP32 sweeps of a mixed solve: G(x) <- g(x) G(x), rows 0,1 kept (12 reals),
 // from Gold into Gnew (the update then forms G(x) U0 G(x+mu)^dagger at x and
 // its neighbours from Gnew; the old G stays readable for those neighbours).
-template <class T, class TF, bool EXACT>
+// g and the product are formed and reunitarised in FP64 (accumulate_G).
+template <bool EXACT>
 __global__ void __launch_bounds__(256)
-    k_gauge_acc(geom g, const vec2_t<TF> *__restrict__ LD, const vec2_t<T> *__restrict__ Gold,
-                vec2_t<T> *__restrict__ Gnew, T c, const dev_status *__restrict__ status) {
+    k_gauge_acc(geom g, const float2 *__restrict__ LD, const float2 *__restrict__ Gold,
+                float2 *__restrict__ Gnew, double c, const dev_status *__restrict__ status) {
     if (status->done) return;
     const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.V) return;
-    const cpx<T> f0 = cvt<T>(ld<TF>(LD + s)), f1 = cvt<T>(ld<TF>(LD + g.S + s)),
-                 f2 = cvt<T>(ld<TF>(LD + 2 * g.S + s)), f3 = cvt<T>(ld<TF>(LD + 3 * g.S + s));
-    mat3<T> gx;
-    if constexpr (EXACT) gx = gauge_exp_from_entries<T>(f0, f1, f2, f3, c);
-    else gx = gauge_from_entries<T>(f0, f1, f2, f3, c);
-    mat3<T> G0;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) G0.e[k / 3][k % 3] = ld<T>(Gold + (long)k * g.S + s);
-    rebuild_row2(G0);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            cpx<T> acc = cmul(gx.e[i][0], G0.e[0][j]);
-            acc = cmac(acc, gx.e[i][1], G0.e[1][j]);
-            acc = cmac(acc, gx.e[i][2], G0.e[2][j]);
-            st<T>(Gnew + (long)(3 * i + j) * g.S + s, acc);
-        }
+    accumulate_G<EXACT>(ld<float>(LD + s), ld<float>(LD + g.S + s), ld<float>(LD + 2 * g.S + s),
+                        ld<float>(LD + 3 * g.S + s), c, Gold, Gnew, g.S, s);
 }
 
 // The Fourier field is FP32 for FP32 sweeps and, when g.ff32 is set, for FP64
@@ -916,16 +903,14 @@ hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void 
     if (fp.enabled) k_finalize<<<1, FIN_BLOCK, 0, st>>>(partials, site_blocks(g.V), status, fp);
     return hipGetLastError();
 }
-hipError_t launch_gauge_acc(const geom &g, const void *LD, const void *Gold, void *Gnew, float c,
+hipError_t launch_gauge_acc(const geom &g, const void *LD, const void *Gold, void *Gnew, double c,
                             bool exact, const dev_status *status, hipStream_t st) {
     if (g.nc != 3) return hipErrorInvalidValue;
     auto LDp = static_cast<const float2 *>(LD);
     auto Go = static_cast<const float2 *>(Gold);
     auto Gn = static_cast<float2 *>(Gnew);
-    if (exact)
-        k_gauge_acc<float, float, true><<<nblk(g.V, 256), 256, 0, st>>>(g, LDp, Go, Gn, c, status);
-    else
-        k_gauge_acc<float, float, false><<<nblk(g.V, 256), 256, 0, st>>>(g, LDp, Go, Gn, c, status);
+    if (exact) k_gauge_acc<true><<<nblk(g.V, 256), 256, 0, st>>>(g, LDp, Go, Gn, c, status);
+    else k_gauge_acc<false><<<nblk(g.V, 256), 256, 0, st>>>(g, LDp, Go, Gn, c, status);
     return hipGetLastError();
 }
 

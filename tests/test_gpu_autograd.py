@@ -138,3 +138,43 @@ def test_autograd_functions(lgf_gpu):
     th.backward()
     _, gref = oracle.theta_grad(U)
     assert np.max(np.abs(cpu(eps.grad) - gref)) < 1e-12 * np.max(np.abs(gref))
+
+
+def test_forward_launches_no_gradient_kernel(lgf_gpu, monkeypatch):
+    """The gradient entry points (the only callers of the gradient kernels) run
+    in backward, never in forward, with or without grad mode."""
+    import torch
+
+    L = (4, 4, 4, 4)
+    U, _ = inputs.make_config(L, 0.5, 51)
+    Ug = gpu(U)
+    om = gpu(inputs.random_omega(L, 0.3, 52)).requires_grad_(True)
+    eps = torch.zeros((4,) + inputs.site_shape(L) + (8,), dtype=torch.float64,
+                      device="cuda", requires_grad=True)
+    calls = []
+    Ctx = lgf_gpu.Context
+    orig_f, orig_t = Ctx.functional_omega_grad, Ctx.theta_grad
+
+    def spy_f(self, *a, **k):
+        calls.append("omega_grad")
+        return orig_f(self, *a, **k)
+
+    def spy_t(self, U, eps=None, need_grad=True):
+        if need_grad:
+            calls.append("theta_grad")
+        return orig_t(self, U, eps, need_grad)
+
+    monkeypatch.setattr(Ctx, "functional_omega_grad", spy_f)
+    monkeypatch.setattr(Ctx, "theta_grad", spy_t)
+    with torch.no_grad():
+        F0 = lgf_gpu.LandauF.apply(om, Ug)
+        th0 = lgf_gpu.LandauTheta.apply(eps, Ug)
+    F = lgf_gpu.LandauF.apply(om, Ug)
+    th = lgf_gpu.LandauTheta.apply(eps, Ug)
+    assert calls == []
+    assert abs(float(F0) - oracle.functional_omega(U, cpu(om))) < 1e-13
+    assert float(F) == float(F0) and float(th) == float(th0)
+    (F + th).backward()
+    assert sorted(calls) == ["omega_grad", "theta_grad"]
+    _, ref = oracle.functional_omega_grad(U, cpu(om))
+    assert np.max(np.abs(cpu(om.grad) - ref)) < 1e-12 * np.max(np.abs(ref))

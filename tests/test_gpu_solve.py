@@ -56,6 +56,7 @@ def test_solve_matches_oracle(lgf_gpu, L, eps, seed, tol, precision):
         assert abs(r.iterations - ref["iterations"]) <= 1
     else:
         assert r.fp32_iterations > 0 and r.iterations > r.fp32_iterations
+        assert r.iterations <= ref["iterations"] + 2
 
 
 def test_history_monotone_and_consistent(lgf_gpu):
@@ -119,19 +120,43 @@ def test_bad_arguments_raise(lgf_gpu):
         lgf_gpu.fix(U.cpu(), 0.08, 1e-15)
 
 
-def test_mixed_iterate_applies_accumulated_transformation(lgf_gpu):
-    """A mixed-precision context runs FP32 sweeps and applies the accumulated
-    transformation to the FP64 input: the result is exactly on the gauge orbit
-    and close (FP32 accuracy) to the FP64 trajectory."""
-    U, _ = inputs.make_config((8, 8, 8, 8), 0.5, 35)
+# the FP32 sweeps' kernels by plane shape: register columns with G accumulated
+# in the inverse (x,y) pass (8 and 32 wide), the 4-field LDS kernel for wider
+# planes with register spans up to 16 (48 wide) and 32 (Ly = 48 beside Lx = 32)
+@pytest.mark.parametrize("L,seed", [((8, 8, 8, 8), 35), ((32, 8, 4, 4), 36), ((48, 4, 4, 6), 37),
+                                    ((32, 48, 2, 2), 38)])
+def test_mixed_iterate_applies_accumulated_transformation(lgf_gpu, L, seed):
+    """FP32-phase lockstep: a mixed-precision context runs FP32 sweeps and
+    applies the accumulated transformation to the FP64 input, so the result is
+    exactly on the gauge orbit and follows the FP64 trajectory of the oracle to
+    FP32 accuracy, over a step far larger than that accuracy."""
+    U, _ = inputs.make_config(L, 0.5, seed)
     Ug = gpu(U)
-    lgf_gpu.iterate(Ug, ALPHA, 6, precision="mixed")
+    r = lgf_gpu.iterate(Ug, ALPHA, 6, precision="mixed")
+    assert r.iterations == 6 and r.fp32_iterations == 6
     out = cpu(Ug)
     assert abs(oracle.plaquette(out) - oracle.plaquette(U)) < 1e-13
-    mu, _ = oracle.unitarity(out)
-    assert mu < 1e-14
+    mu, md = oracle.unitarity(out)
+    assert mu < 1e-14 and md < 1e-14
     ref = oracle.iterate(U, ALPHA, 6)
+    assert np.max(np.abs(ref - U)) > 0.1
     assert np.max(np.abs(out - ref)) < 1e-4
+    assert r.theta == pytest.approx(oracle.theta(out), rel=1e-12)
+
+
+def test_fixed_count_runs_every_sweep_even_when_theta_rises(lgf_gpu):
+    """lgf_iterate has no stopping test: with alpha above 2/p2max theta
+    rises every sweep (a solve would stop as diverging), and all n sweeps are
+    still applied, in lockstep with the oracle."""
+    U = inputs.abelian_config((8, 8, 8, 8), 1e-4, 39)
+    Ug = gpu(U)
+    r = lgf_gpu.iterate(Ug, 0.2, 12)
+    assert r.status == 0 and r.iterations == 12
+    ref = oracle.iterate(U, 0.2, 12)
+    assert oracle.theta(ref) > 1e4 * oracle.theta(U)
+    assert np.max(np.abs(cpu(Ug) - ref)) < 1e-10
+    rs = lgf_gpu.fix(gpu(U), 0.2, 1e-15, max_iter=12)
+    assert rs.status == lgf_gpu.LGF_DIVERGING and rs.iterations < 12
 
 
 # ------------------------------------------- plain (unaccelerated) steepest descent

@@ -223,8 +223,28 @@ int lgf_history(lgf_ctx *ctx, double *F, double *theta, int cap, int *count);
  * 2 (x,y) inverse FFT, 3 update + next divergence, 4 finalize. */
 int lgf_profile(lgf_ctx *ctx, const double *U, double alpha, int n_iter, double *kernel_ms);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): F_U[1] and
+ * theta of the SU(3) links U without a context -- the values lgf_functional
+ * (g == NULL) and lgf_theta return, from the same arithmetic in the same
+ * summation order.  L: as for lgf_create, with V <= LGF_NOALLOC_MAX_SITES.
+ * U: DEVICE complex128 links (rows 0,1 of each link read).  out: DEVICE
+ * pointer to 2 doubles that receive {F, theta}.  The work is enqueued on
+ * `stream` (a hipStream_t, NULL: the null stream) of the current HIP device
+ * and the call returns without synchronising.  It allocates nothing: the
+ * per-block partial sums live in a fixed device array of the library
+ * (LGF_NOALLOC_MAX_SITES/256 pairs of doubles, 2 MiB, on each device it is
+ * used on, held until the process ends), looked up on the first call on a
+ * device.  Every call on a device shares that array, so calls that overlap in
+ * time on one device race: serialise them (e.g. one stream).  LGF_ERR_ARG
+ * (nothing enqueued) for a NULL pointer, an unsupported extent or a larger
+ * lattice; LGF_ERR_DEVICE if the array cannot be looked up or the launch
+ * fails.  Messages via lgf_last_error(NULL). */
+#define LGF_NOALLOC_MAX_SITES (1L << 25)
+int lgf_measure_noalloc(const int L[4], const double *U, double *out, void *stream);
+
 /* Message for the last failure on ctx (ctx == NULL: last failure of
- * lgf_create on this thread).  Never NULL. */
+ * lgf_create or lgf_measure_noalloc on this thread).  Never NULL. */
 const char *lgf_last_error(const lgf_ctx *ctx);
 
 #ifdef __cplusplus

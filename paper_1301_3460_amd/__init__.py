@@ -17,7 +17,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "load", "LgfError", "Context", "Result", "fix", "iterate", "functional", "theta",
-    "plaquette", "divergence", "fourier_accelerate", "fft4d", "functional_omega",
+    "plaquette", "measure_noalloc", "divergence", "fourier_accelerate", "fft4d", "functional_omega",
     "functional_omega_grad", "theta_grad", "LandauF", "LandauTheta", "EXPORTS",
 ]
 
@@ -104,6 +104,7 @@ def load(path: str | None = None):
         "lgf_theta_grad": (c.c_int, [vp, vp, vp, dp, vp]),
         "lgf_history": (c.c_int, [vp, vp, vp, c.c_int, ip]),
         "lgf_profile": (c.c_int, [vp, vp, c.c_double, c.c_int, vp]),
+        "lgf_measure_noalloc": (c.c_int, [c.POINTER(c.c_int * 4), vp, vp, vp]),
         "lgf_last_error": (c.c_char_p, [vp]),
     }
     for name, (res, args) in sigs.items():
@@ -403,6 +404,28 @@ def theta(U):
 
 def plaquette(U):
     return _ctx(U).plaquette(U)
+
+
+def measure_noalloc(U, out=None, stream=None):
+    """{F, theta} of SU(3) links U into the float64 CUDA tensor ``out`` (shape
+    (2,)) without a context and without device allocation in the library
+    (lgf_measure_noalloc); enqueued on ``stream`` (default: the current one),
+    not synchronised.  Returns ``out``."""
+    import torch
+
+    lib = load()
+    L = _lattice_of_links(U)
+    up = _check(U, torch.complex128, None, "U")
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=U.device)
+    op = _check(out, torch.float64, (2,), "out")
+    st = stream if stream is not None else torch.cuda.current_stream(U.device)
+    arr = (ctypes.c_int * 4)(*L)
+    with torch.cuda.device(U.device):
+        rc = lib.lgf_measure_noalloc(ctypes.byref(arr), up, op, ctypes.c_void_p(st.cuda_stream))
+    if rc != LGF_OK:
+        raise LgfError(rc, lib.lgf_last_error(None).decode())
+    return out
 
 
 def divergence(U):

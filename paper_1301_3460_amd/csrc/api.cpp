@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -433,6 +434,40 @@ int profile_impl(lgf_ctx *c, const double *U, double alpha, int n, double *ms) {
     return rc;
 }
 
+// ------------------------------------------------- fixed scratch (no allocation)
+
+// Block partial sums of lgf_measure_noalloc: one fixed array per device,
+// resident until the process ends.  Host code must not pass `scratch` itself
+// to a kernel (in host code the name is a stand-in, not a device address);
+// noalloc_scratch looks up each device's address once and keeps it.
+constexpr long NOALLOC_PARTS = LGF_NOALLOC_MAX_SITES / SITE_BLOCK;
+static __device__ __align__(256) double scratch[2 * NOALLOC_PARTS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The current device's address of `scratch` (looked up with that device
+// current on the first call on it).
+int noalloc_scratch(double **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, LGF_ERR_DEVICE, "no HIP device");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(nullptr, LGF_ERR_DEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, LGF_ERR_DEVICE,
+                        std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return LGF_OK;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -460,22 +495,7 @@ int lgf_create_group(lgf_ctx **out, const int L[4], int nc, int precision, void 
         return fail(nullptr, LGF_ERR_ARG, "precision must be LGF_FP64 or LGF_MIXED");
     lgf_ctx *c = new (std::nothrow) lgf_ctx();
     if (!c) return fail(nullptr, LGF_ERR_OOM, "host allocation failed");
-    c->g.Lx = L[0];
-    c->g.Ly = L[1];
-    c->g.Lz = L[2];
-    c->g.Lt = L[3];
-    c->g.V = (long)L[0] * L[1] * L[2] * L[3];
-    c->g.S = c->g.V + SOA_PAD;
-    c->g.nc = nc;
-    c->g.nf = nc == 3 ? 4 : 2;
-    // 64 consecutive xy-sites x 4 t per block where the shape allows it (8x8
-    // xy tiles keep more neighbours in a block, but their short rows cost more
-    // in DRAM efficiency than they save)
-    c->g.tblock = ((long)L[0] * L[1] % 64 == 0 && L[3] % 4 == 0) ? 1 : 0;
-    {
-        const long nseg = (long)L[0] * L[1] / 64;
-        c->g.sgroup = (nseg % 4 == 0) ? 4 : (nseg % 2 == 0) ? 2 : 1;
-    }
+    c->g = make_geom(L, nc);
     c->precision = precision;
     c->stream = static_cast<hipStream_t>(stream);
     if (hipGetDevice(&c->device) != hipSuccess) {
@@ -905,6 +925,27 @@ int lgf_history(lgf_ctx *c, double *F, double *theta, int cap, int *count) {
     if (n > 0 && theta)
         HIPCHK(c, hipMemcpy(theta, c->histT, n * sizeof(double), hipMemcpyDeviceToHost));
     *count = n;
+    return LGF_OK;
+}
+
+int lgf_measure_noalloc(const int L[4], const double *U, double *out, void *stream) {
+    if (!L || !U || !out) return fail(nullptr, LGF_ERR_ARG, "null argument");
+    if (!shape_ok(L))
+        return fail(nullptr, LGF_ERR_ARG, "unsupported lattice extent");
+    const geom g = make_geom(L, 3);
+    if (g.V > LGF_NOALLOC_MAX_SITES)
+        return fail(nullptr, LGF_ERR_ARG,
+                    "lattice of " + std::to_string(g.V) + " sites exceeds the " +
+                        std::to_string((long)LGF_NOALLOC_MAX_SITES) +
+                        " sites of the fixed scratch array");
+    double *partials = nullptr;
+    const int rc = noalloc_scratch(&partials);
+    if (rc) return rc;
+    const hipError_t e =
+        launch_measure_aos(g, U, partials, out, 1.0 / (4.0 * 3.0 * (double)g.V),
+                           1.0 / (3.0 * (double)g.V), static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail(nullptr, LGF_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
     return LGF_OK;
 }
 

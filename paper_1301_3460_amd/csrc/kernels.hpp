@@ -65,6 +65,28 @@ struct geom {
 constexpr int SITE_BLOCK = 256;  // threads per block of the site kernels
 inline int site_blocks(long V) { return (int)((V + SITE_BLOCK - 1) / SITE_BLOCK); }
 
+// Geometry of lattice L = {Lx, Ly, Lz, Lt} for SU(nc): 12-real links, FP64
+// field.  The site-kernel tiling takes 64 consecutive xy-sites x 4 t per
+// block where the shape allows it (8x8 xy tiles keep more neighbours in a
+// block, but their short rows cost more in DRAM efficiency than they save).
+inline geom make_geom(const int L[4], int nc) {
+    geom g{};
+    g.Lx = L[0];
+    g.Ly = L[1];
+    g.Lz = L[2];
+    g.Lt = L[3];
+    g.V = (long)L[0] * L[1] * L[2] * L[3];
+    g.S = g.V + SOA_PAD;
+    g.nc = nc;
+    g.nf = nc == 3 ? 4 : 2;
+    g.nr = 2;
+    g.ff32 = 0;
+    g.tblock = ((long)L[0] * L[1] % 64 == 0 && L[3] % 4 == 0) ? 1 : 0;
+    const long nseg = (long)L[0] * L[1] / 64;
+    g.sgroup = (nseg % 4 == 0) ? 4 : (nseg % 2 == 0) ? 2 : 1;
+    return g;
+}
+
 // All launchers enqueue on `st` and return hipGetLastError().
 template <class T>
 hipError_t launch_pack_links(const double *Uaos, void *L, const geom &g, hipStream_t st);
@@ -128,6 +150,15 @@ hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const
 // si (input) and so (output); to_natural: positions -> natural order
 hipError_t launch_reorder_fields(const geom &g, const double2 *in, long si, double2 *out, long so,
                                  int to_natural, hipStream_t st);
+
+// F = normF sum Re Tr U and theta = normT sum Tr[Delta Delta^+] of the
+// complex128 AoS links Uaos ([4][V][3][3], rows 0,1 read) into out[0..1]
+// (device), with the block partials in `partials` (site_blocks(V) pairs): the
+// arithmetic of launch_div_reduce + launch_reduce_only on packed links, in
+// the same order, without packing them (nothing is allocated or written
+// besides partials and out).
+hipError_t launch_measure_aos(const geom &g, const double *Uaos, double *partials, double *out,
+                              double normF, double normT, hipStream_t st);
 
 hipError_t launch_finalize(const double *partials, int nparts, dev_status *status,
                            const fin_params &fp, hipStream_t st);

@@ -186,6 +186,26 @@ __device__ __forceinline__ void finalize_state(double A, double B, dev_status *s
 
 // TF: real type of the Fourier field (T, or float for FP64 sweeps whose field
 // is held in FP32)
+// Delta(x) of the links link(mu, site), packed into the 4 field entries f;
+// tr = sum_mu Re Tr U_mu(x); returns Tr[Delta Delta^dagger].
+template <class T, class LinkFn>
+__device__ __forceinline__ T divergence_at(const geom &g, long s, LinkFn link, cpx<T> (&f)[4],
+                                           T &tr) {
+    const nbr n = neighbours(g, s);
+    xacc<T> X;
+    xacc_zero(X);
+    tr = 0;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        mat3<T> u = link(mu, s);
+        tr += retrace(u);
+        xacc_add(X, u, T(-1));
+        mat3<T> um = link(mu, n.m[mu]);
+        xacc_add(X, um, T(1));
+    }
+    return delta_pack(X, f[0], f[1], f[2], f[3]);
+}
+
 template <class T, class TF, int NR>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_div_reduce(geom g, const vec2_t<T> *__restrict__ L, vec2_t<TF> *__restrict__ D,
@@ -194,25 +214,36 @@ __global__ void __launch_bounds__(SITE_BLOCK)
     const long s = block_site(g, blockIdx.x, gridDim.x, threadIdx.x);
     double fs = 0, ts = 0;
     if (s < g.V) {
-        const nbr n = neighbours(g, s);
-        xacc<T> X;
-        xacc_zero(X);
-        T tr = 0;
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            mat3<T> u = load_link<T, NR>(L, g.S, mu, s);
-            tr += retrace(u);
-            xacc_add(X, u, T(-1));
-            mat3<T> um = load_link<T, NR>(L, g.S, mu, n.m[mu]);
-            xacc_add(X, um, T(1));
-        }
-        cpx<T> f0, f1, f2, f3;
-        ts = (double)delta_pack(X, f0, f1, f2, f3);
+        cpx<T> f[4];
+        T tr;
+        ts = (double)divergence_at<T>(
+            g, s, [&](int mu, long x) { return load_link<T, NR>(L, g.S, mu, x); }, f, tr);
         fs = (double)tr;
-        st<TF>(D + s, cvt<TF>(f0));
-        st<TF>(D + g.S + s, cvt<TF>(f1));
-        st<TF>(D + 2 * g.S + s, cvt<TF>(f2));
-        st<TF>(D + 3 * g.S + s, cvt<TF>(f3));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) st<TF>(D + k * g.S + s, cvt<TF>(f[k]));
+    }
+    block_sum2<SITE_BLOCK>(fs, ts, partials, blockIdx.x);
+}
+
+// k_div_reduce<double, double, 2> reading the caller's AoS links directly
+// (rows 0,1; row 2 rebuilt as a 12-real load does) and storing no field.
+__global__ void __launch_bounds__(SITE_BLOCK)
+    k_measure_aos(geom g, const double2 *__restrict__ U, double *__restrict__ partials) {
+    const long s = block_site(g, blockIdx.x, gridDim.x, threadIdx.x);
+    double fs = 0, ts = 0;
+    if (s < g.V) {
+        auto link = [&](int mu, long x) {
+            mat3<double> m;
+            const double2 *u = U + ((long)mu * g.V + x) * 9;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) m.e[k / 3][k % 3] = mk<double>(u[k].x, u[k].y);
+            rebuild_row2(m);
+            return m;
+        };
+        cpx<double> f[4];
+        double tr;
+        ts = divergence_at<double>(g, s, link, f, tr);
+        fs = tr;
     }
     block_sum2<SITE_BLOCK>(fs, ts, partials, blockIdx.x);
 }
@@ -356,6 +387,17 @@ __global__ void k_status_reset(dev_status *status, int hist_base) {
     st.hist_base = hist_base;
     st.since_min = 0;
     *status = st;
+}
+
+__global__ void __launch_bounds__(FIN_BLOCK)
+    k_measure_finalize(const double *__restrict__ partials, int nparts, double *out2,
+                       double normF, double normT) {
+    double A, B;
+    fixed_order_sum<FIN_BLOCK>(partials, nparts, A, B);
+    if (threadIdx.x == 0) {
+        out2[0] = A * normF;
+        out2[1] = B * normT;
+    }
 }
 
 __global__ void __launch_bounds__(FIN_BLOCK)
@@ -940,6 +982,14 @@ hipError_t launch_status_reset(dev_status *status, int hist_base, hipStream_t st
 
 hipError_t launch_reduce_only(const double *partials, int nparts, double *out2, hipStream_t st) {
     k_reduce_only<<<1, FIN_BLOCK, 0, st>>>(partials, nparts, out2);
+    return hipGetLastError();
+}
+
+hipError_t launch_measure_aos(const geom &g, const double *Uaos, double *partials, double *out,
+                              double normF, double normT, hipStream_t st) {
+    const int nb = site_blocks(g.V);
+    k_measure_aos<<<nb, SITE_BLOCK, 0, st>>>(g, reinterpret_cast<const double2 *>(Uaos), partials);
+    k_measure_finalize<<<1, FIN_BLOCK, 0, st>>>(partials, nb, out, normF, normT);
     return hipGetLastError();
 }
 

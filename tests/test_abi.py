@@ -77,3 +77,15 @@ def test_header_documents_every_entry_point():
         assert m, name
         idx = m.start()
         assert "*/" in text[max(0, idx - 1200):idx], name
+
+
+def test_measure_noalloc_rejects_arguments_before_touching_the_device():
+    lib = lgf.load()
+    out = ctypes.c_void_p(16)  # never dereferenced: the call fails its argument checks
+    big = (ctypes.c_int * 4)(128, 128, 64, 64)  # 2^26 sites, beyond the fixed scratch
+    assert lib.lgf_measure_noalloc(ctypes.byref(big), out, out, None) == lgf.LGF_ERR_ARG
+    assert b"sites" in lib.lgf_last_error(None)
+    bad = (ctypes.c_int * 4)(5, 4, 4, 4)
+    assert lib.lgf_measure_noalloc(ctypes.byref(bad), out, out, None) == lgf.LGF_ERR_ARG
+    ok = (ctypes.c_int * 4)(4, 4, 4, 4)
+    assert lib.lgf_measure_noalloc(ctypes.byref(ok), None, out, None) == lgf.LGF_ERR_ARG

@@ -23,8 +23,11 @@
  *   U_mu(x) <- g(x) U_mu(x) g(x+mu)^dagger  (all links at once)
  *
  * Conventions shared by every entry point
- *   Lattice      L[4] = {Lx, Ly, Lz, Lt}; each extent is one of
- *                2 3 4 6 8 12 16 24 32 48 64 96 128.  Periodic boundaries.
+ *   Lattice      L[4] = {Lx, Ly, Lz, Lt}; each extent a product 2^a 3^b
+ *                with 2 <= L_mu <= 256 (2 3 4 6 8 9 12 16 18 24 27 32 36 48
+ *                54 64 72 81 96 108 128 144 162 192 216 243 256: the
+ *                extents of the hand-written mixed-radix transform), fewer
+ *                than 2^31 sites.  Periodic boundaries.
  *                Site index s = x + Lx*(y + Ly*(z + Lz*t)).
  *   Links U      DEVICE pointer to complex128 data (interleaved re, im)
  *                laid out [4][Lt][Lz][Ly][Lx][3][3] (mu = x, y, z, t), i.e. a
@@ -89,8 +92,10 @@ typedef struct {
  * HIP device at creation is the context's device.  *out receives the context
  * (NULL on failure).  Allocates the context's device scratch (about 1 GiB at
  * 32^4 FP64).  LGF_ERR_ARG for a NULL pointer, an unsupported extent or
- * precision; LGF_ERR_OOM if the scratch does not fit; LGF_ERR_DEVICE if no
- * HIP device is current.  lgf_last_error(NULL) explains a failure. */
+ * precision, or a lattice whose transform passes would exceed the LDS or grid
+ * limits of one kernel launch; LGF_ERR_OOM if the scratch does not fit;
+ * LGF_ERR_DEVICE if no HIP device is current.  lgf_last_error(NULL) explains a
+ * failure. */
 int lgf_create(lgf_ctx **out, const int L[4], int precision, void *stream);
 
 /* As lgf_create for the gauge group SU(nc), nc = 3 or 2 (the paper's

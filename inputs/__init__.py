@@ -40,6 +40,8 @@ CONFIG_SEEDS = {
     ("4^4", 0.5): 4005,
     ("16^4", 0.5): 1605,
     ("48^3x96", 0.45): 4845,
+    ("36^3x72", 0.45): 3672,
+    ("27^4", 0.45): 2745,
     ("su2 8^4", 0.5): 2801,
     ("su2 16^4", 0.5): 2161,
     ("su2 32^4", 0.45): 2324,

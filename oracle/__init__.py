@@ -19,16 +19,26 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_PLAIN = os.path.join(_HERE, "liboracle.so")
+# AddressSanitizer + UndefinedBehaviorSanitizer build, used instead when
+# LGF_ORACLE_SANITIZED=1 (the process must preload gcc's libasan.so)
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+_SANITIZED = os.environ.get("LGF_ORACLE_SANITIZED") == "1"
+_LIB = _LIB_SAN if _SANITIZED else _LIB_PLAIN
 
 BUILD_CMD = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
-             "-fcx-limited-range", _SRC, "-o", _LIB, "-lm"]
+             "-fcx-limited-range", _SRC, "-o", _LIB_PLAIN, "-lm"]
+SAN_BUILD_CMD = ["gcc", "-O1", "-g", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                 "-fcx-limited-range", "-fsanitize=address,undefined",
+                 "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+                 _SRC, "-o", _LIB_SAN, "-lm"]
 
 
-def build() -> str:
-    """Compile the oracle with gcc (always recompiles)."""
-    subprocess.run(BUILD_CMD, check=True)
-    return _LIB
+def build(sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (always recompiles); sanitize: the
+    ASan/UBSan build liboracle_san.so."""
+    subprocess.run(SAN_BUILD_CMD if sanitize else BUILD_CMD, check=True)
+    return _LIB_SAN if sanitize else _LIB_PLAIN
 
 
 _lib = None
@@ -43,7 +53,7 @@ def _load():
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build()
+        build(sanitize=_SANITIZED)
     lib = ctypes.CDLL(_LIB)
     sig = {
         "orc_set_threads": (None, [_c.c_int]),

@@ -67,7 +67,8 @@ _lib = None
 
 
 def load(path: str | None = None):
-    """Load liblgf.so.  torch is imported first so that the library binds to the
+    """Load liblgf.so (or the library at ``path`` / $LGF_LIB, e.g. the host-side
+    sanitizer build).  torch is imported first so that the library binds to the
     HIP runtime torch already uses (one runtime: shared pointers and streams).
     Raises if the library has not been built -- there is no fallback."""
     global _lib
@@ -75,7 +76,7 @@ def load(path: str | None = None):
         return _lib
     import torch  # noqa: F401  (loads the HIP runtime)
 
-    p = path or LIB_PATH
+    p = path or os.environ.get("LGF_LIB") or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"{p} is missing: build it with `python -m paper_1301_3460_amd.build`")
     lib = ctypes.CDLL(p)

@@ -27,33 +27,61 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer build (the CPU
+# part of every translation unit only; device code is compiled as usual):
+# liblgf_san.so, for host-only checks of the C ABI, loaded in a process that
+# preloads clang's shared ASan runtime (see sanitizer_runtime()).
+SAN_FLAGS = ["-Xarch_host", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer"]
+SAN_LINK = ["-shared-libsan", "-Xarch_host", "-fsanitize=address",
+            "-Xarch_host", "-fsanitize=undefined"]
+LIB_SAN = os.path.join(HERE, "liblgf_san.so")
+
+
+def sanitizer_runtime() -> str:
+    """Path of clang's shared ASan runtime that a process loading
+    liblgf_san.so must preload."""
+    out = subprocess.run(["hipcc", "-print-file-name=libclang_rt.asan-x86_64.so"],
+                         capture_output=True, text=True, check=True).stdout.strip()
+    if not os.path.isabs(out):
+        rd = subprocess.run(["hipcc", "-print-resource-dir"], capture_output=True, text=True,
+                            check=True).stdout.strip()
+        out = os.path.join(rd, "lib", "linux", "libclang_rt.asan-x86_64.so")
+    return out
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
     """Compile every source (in parallel, one hipcc per translation unit) and
-    link liblgf.so.  Always recompiles."""
+    link liblgf.so (sanitize: liblgf_san.so with host-side ASan/UBSan).
+    Always recompiles."""
     from concurrent.futures import ThreadPoolExecutor
 
-    objdir = os.path.join(HERE, "_build")
+    objdir = os.path.join(HERE, "_build_san" if sanitize else "_build")
+    lib = LIB_SAN if sanitize else LIB
     os.makedirs(objdir, exist_ok=True)
     objs = [os.path.join(objdir, os.path.basename(src) + ".o") for src in SOURCES]
+    extra = SAN_FLAGS if sanitize else []
 
     def compile_one(pair):
         src, obj = pair
-        cmd = ["hipcc", *HIPCC_FLAGS, "-c", "-x", "hip", src, "-o", obj]
+        cmd = ["hipcc", *HIPCC_FLAGS, *extra, "-c", "-x", "hip", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
 
     with ThreadPoolExecutor(len(SOURCES)) as ex:
         list(ex.map(compile_one, zip(SOURCES, objs)))
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    tmp = lib + ".tmp"
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *(SAN_LINK if sanitize else []),
+           *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, sanitize="--sanitize" in sys.argv[1:])
     sys.exit(0)

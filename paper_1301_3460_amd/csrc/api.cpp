@@ -53,12 +53,13 @@ struct lgf_ctx {
     float2 *G32 = nullptr;
     // Fourier fields (4 complex per site), FP64 size; FP32 views alias them
     double2 *D64[2] = {nullptr, nullptr};
-    // tables
+    // tables: per-axis twiddles (x, y, z, t tables one after the other) and
+    // per-axis p2 by transform position
     double2 *tw64 = nullptr;
     float2 *tw32 = nullptr;
     double *pt64 = nullptr;
     float *pt32 = nullptr;
-    zt_plan zt64{}, zt32{};
+    fft_plan plan64{}, plan32{};  // how the transform is split into passes
     // reductions and control
     double *partials = nullptr;
     int nparts = 0;
@@ -114,15 +115,20 @@ fin_params finp(const lgf_ctx *c, bool enabled, double tol = 0, int max_iter = 0
     return f;
 }
 
-// tw[j] = exp(-2 pi i j / TW_M), long double
-template <class V2> std::vector<V2> make_twiddles() {
-    std::vector<V2> t(TW_M);
+// The axis tables exp(-2 pi i j / L_mu), j < L_mu, of x, y, z and t one after
+// the other, from long double.
+template <class V2> std::vector<V2> make_twiddles(const geom &g) {
+    const int L[4] = {g.Lx, g.Ly, g.Lz, g.Lt};
+    std::vector<V2> t;
     const long double twopi = 6.283185307179586476925286766559005768L;
-    for (int j = 0; j < TW_M; ++j) {
-        long double a = twopi * (long double)j / (long double)TW_M;
-        t[j].x = (decltype(t[j].x))cosl(a);
-        t[j].y = (decltype(t[j].y))(-sinl(a));
-    }
+    for (int mu = 0; mu < 4; ++mu)
+        for (int j = 0; j < L[mu]; ++j) {
+            const long double a = twopi * (long double)j / (long double)L[mu];
+            V2 v;
+            v.x = (decltype(v.x))cosl(a);
+            v.y = (decltype(v.y))(-sinl(a));
+            t.push_back(v);
+        }
     return t;
 }
 
@@ -145,10 +151,15 @@ std::vector<long double> make_p2_tables(const geom &g, long double &p2max) {
     return t;
 }
 
+// Every extent 2^a 3^b in [2, FFT_MAX_EXTENT]; the volume below 2^31 sites
+// (site coordinates are decoded in 32-bit arithmetic).
 bool shape_ok(const int L[4]) {
-    for (int mu = 0; mu < 4; ++mu)
+    long V = 1;
+    for (int mu = 0; mu < 4; ++mu) {
         if (!fft_supported(L[mu])) return false;
-    return true;
+        V *= L[mu];
+    }
+    return V < (1L << 31);
 }
 
 // ------------------------------------------------------------------ sweep
@@ -159,14 +170,14 @@ template <> struct prec<double> {
     static void *field(lgf_ctx *c, int i) { return c->D64[i]; }
     static const void *tw(lgf_ctx *c) { return c->tw64; }
     static const double *pt(lgf_ctx *c) { return c->pt64; }
-    static const zt_plan &W(lgf_ctx *c) { return c->zt64; }
+    static const fft_plan &W(lgf_ctx *c) { return c->plan64; }
 };
 template <> struct prec<float> {
     static void *links(lgf_ctx *c, int i) { return c->L32[i]; }
     static void *field(lgf_ctx *c, int i) { return c->D64[i]; }
     static const void *tw(lgf_ctx *c) { return c->tw32; }
     static const float *pt(lgf_ctx *c) { return c->pt32; }
-    static const zt_plan &W(lgf_ctx *c) { return c->zt32; }
+    static const fft_plan &W(lgf_ctx *c) { return c->plan32; }
 };
 
 // The accumulated transformation of the FP32 sweeps after n of them.  SU(3)
@@ -199,17 +210,19 @@ template <class T> bool field32(const lgf_ctx *c) {
 hipError_t transform_pass(lgf_ctx *c, bool f32, int pass, void *D) {
     const double k = c->p2max / (double)c->g.V;
     if (f32) {
-        if (pass == 0) return launch_fft_xy<float>(c->g, D, -1, c->tw32, c->status, c->stream);
+        if (pass == 0)
+            return launch_fft_xy<float>(c->g, D, -1, c->tw32, c->plan32, c->status, c->stream);
         if (pass == 1)
-            return launch_fft_zt<float>(c->g, D, 0, c->tw32, c->pt32, (float)k, c->zt32,
+            return launch_fft_zt<float>(c->g, D, 0, c->tw32, c->pt32, (float)k, c->plan32,
                                         c->status, c->stream);
-        return launch_fft_xy<float>(c->g, D, +1, c->tw32, c->status, c->stream);
+        return launch_fft_xy<float>(c->g, D, +1, c->tw32, c->plan32, c->status, c->stream);
     }
-    if (pass == 0) return launch_fft_xy<double>(c->g, D, -1, c->tw64, c->status, c->stream);
+    if (pass == 0)
+        return launch_fft_xy<double>(c->g, D, -1, c->tw64, c->plan64, c->status, c->stream);
     if (pass == 1)
-        return launch_fft_zt<double>(c->g, D, 0, c->tw64, c->pt64, k, c->zt64, c->status,
+        return launch_fft_zt<double>(c->g, D, 0, c->tw64, c->pt64, k, c->plan64, c->status,
                                      c->stream);
-    return launch_fft_xy<double>(c->g, D, +1, c->tw64, c->status, c->stream);
+    return launch_fft_xy<double>(c->g, D, +1, c->tw64, c->plan64, c->status, c->stream);
 }
 
 // Pass `pass` (0..2) of sweep `cur`'s transform of field D (none without the
@@ -220,8 +233,8 @@ template <class T>
 hipError_t sweep_pass(lgf_ctx *c, int cur, void *D, T half_alpha, int pass) {
     if constexpr (std::is_same<T, float>::value) {
         if (c->g.nc == 3 && pass == 2) {
-            if (c->accelerate && xy_acc_fusable<float>(c->g))
-                return launch_fft_xy_inv_acc<float>(c->g, D, c->tw32, acc_G(c, cur),
+            if (c->accelerate && xy_acc_fusable<float>(c->g, c->plan32))
+                return launch_fft_xy_inv_acc<float>(c->g, D, c->tw32, c->plan32, acc_G(c, cur),
                                                     acc_G(c, cur ^ 1), c->half_alpha, c->exact_exp,
                                                     c->status, c->stream);
             if (c->accelerate) {
@@ -470,6 +483,19 @@ int noalloc_scratch(double **out) {
 
 }  // namespace
 
+namespace lgf {
+bool fft_plan_fits(const fft_plan &p) {
+    constexpr size_t LDS_MAX = 160 * 1024;
+    auto axis_ok = [&](const axis_plan &a) {
+        return a.lds <= LDS_MAX && (a.nslice + a.B - 1) / a.B <= 65535;
+    };
+    if (p.xy != 2 && p.lds_xy > LDS_MAX) return false;
+    if (p.xy == 2 && !(axis_ok(p.x) && axis_ok(p.y))) return false;
+    if (p.rc) return p.lds <= LDS_MAX;
+    return axis_ok(p.z) && axis_ok(p.t);
+}
+}  // namespace lgf
+
 // =================================================================== C ABI
 
 extern "C" {
@@ -484,12 +510,14 @@ int lgf_create_group(lgf_ctx **out, const int L[4], int nc, int precision, void 
     if (nc != 2 && nc != 3) return fail(nullptr, LGF_ERR_ARG, "gauge group must be SU(2) or SU(3)");
     if (!shape_ok(L))
         return fail(nullptr, LGF_ERR_ARG,
-                    "unsupported lattice extent (allowed: 2 3 4 6 8 12 16 24 32 48 64 96 128)");
+                    "unsupported lattice extent (allowed: 2^a 3^b from 2 to 256, fewer than "
+                    "2^31 sites)");
     {
-        geom g0{L[0], L[1], L[2], L[3], 1};
-        if (plan_zt<double>(g0, ZT_LDS_BUDGET).lds > 160 * 1024 ||
-            fft_xy_lds_bytes<double>(g0) > 160 * 1024)
-            return fail(nullptr, LGF_ERR_ARG, "lattice planes too large for one LDS tile");
+        const geom g0 = make_geom(L, nc);
+        if (!fft_plan_fits(plan_fft<double>(g0, ZT_LDS_BUDGET)) ||
+            !fft_plan_fits(plan_fft<float>(g0, ZT_LDS_BUDGET)))
+            return fail(nullptr, LGF_ERR_ARG, "lattice extent: transform passes exceed the "
+                                              "LDS or grid limits");
     }
     if (precision != LGF_FP64 && precision != LGF_MIXED)
         return fail(nullptr, LGF_ERR_ARG, "precision must be LGF_FP64 or LGF_MIXED");
@@ -513,9 +541,9 @@ int lgf_create_group(lgf_ctx **out, const int L[4], int nc, int precision, void 
     // accumulated transformation (mixed): row 0 and 1 (SU(3)) or row 0 (SU(2))
     if (precision == LGF_MIXED)
         ok = ok && alloc((void **)&c->G32, (size_t)(nc == 3 ? 6 : 2) * S * sizeof(float2));
-    ok = ok && alloc((void **)&c->tw64, TW_M * sizeof(double2));
-    ok = ok && alloc((void **)&c->tw32, TW_M * sizeof(float2));
     const int nt = L[0] + L[1] + L[2] + L[3];
+    ok = ok && alloc((void **)&c->tw64, nt * sizeof(double2));
+    ok = ok && alloc((void **)&c->tw32, nt * sizeof(float2));
     ok = ok && alloc((void **)&c->pt64, nt * sizeof(double));
     ok = ok && alloc((void **)&c->pt32, nt * sizeof(float));
     ok = ok && alloc((void **)&c->partials, (size_t)2 * c->nparts * sizeof(double));
@@ -530,23 +558,23 @@ int lgf_create_group(lgf_ctx **out, const int L[4], int nc, int precision, void 
         return fail(nullptr, LGF_ERR_OOM, "out of device memory");
     }
 
-    auto tw64 = make_twiddles<double2>();
-    auto tw32 = make_twiddles<float2>();
+    auto tw64 = make_twiddles<double2>(c->g);
+    auto tw32 = make_twiddles<float2>(c->g);
     long double p2max = 0;
     auto pt = make_p2_tables(c->g, p2max);
     c->p2max = (double)p2max;
     std::vector<double> pt64(pt.begin(), pt.end());
     std::vector<float> pt32(pt.begin(), pt.end());
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = hipMemcpy(c->tw64, tw64.data(), TW_M * sizeof(double2), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c->tw32, tw32.data(), TW_M * sizeof(float2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->tw64, tw64.data(), nt * sizeof(double2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->tw32, tw32.data(), nt * sizeof(float2), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->pt64, pt64.data(), nt * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->pt32, pt32.data(), nt * sizeof(float), hipMemcpyHostToDevice);
-    c->zt64 = plan_zt<double>(c->g, ZT_LDS_BUDGET);
-    c->zt32 = plan_zt<float>(c->g, ZT_LDS_BUDGET);
+    c->plan64 = plan_fft<double>(c->g, ZT_LDS_BUDGET);
+    c->plan32 = plan_fft<float>(c->g, ZT_LDS_BUDGET);
     // best effort: a launch that still exceeds the limit reports its own error
-    fft_set_max_lds<double>(c->g, c->zt64);
-    fft_set_max_lds<float>(c->g, c->zt32);
+    fft_set_max_lds<double>(c->g, c->plan64);
+    fft_set_max_lds<float>(c->g, c->plan32);
     if (e != hipSuccess) {
         std::string m = std::string("initialisation failed: ") + hipGetErrorString(e);
         lgf_destroy(c);
@@ -803,10 +831,12 @@ int lgf_fourier_accelerate(lgf_ctx *c, const double *D, double *LD) {
     if (rc) return rc;
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
     HIPCHK(c, launch_field_from_matrix(D, c->D64[0], c->g.V, c->g.S, c->stream));
-    HIPCHK(c, launch_fft_xy<double>(c->g, c->D64[0], -1, c->tw64, c->status, c->stream));
+    HIPCHK(c, launch_fft_xy<double>(c->g, c->D64[0], -1, c->tw64, c->plan64, c->status,
+                                    c->stream));
     HIPCHK(c, launch_fft_zt<double>(c->g, c->D64[0], 0, c->tw64, c->pt64,
-                                    c->p2max / (double)c->g.V, c->zt64, c->status, c->stream));
-    HIPCHK(c, launch_fft_xy<double>(c->g, c->D64[0], +1, c->tw64, c->status, c->stream));
+                                    c->p2max / (double)c->g.V, c->plan64, c->status, c->stream));
+    HIPCHK(c, launch_fft_xy<double>(c->g, c->D64[0], +1, c->tw64, c->plan64, c->status,
+                                    c->stream));
     HIPCHK(c, launch_matrix_from_field(c->D64[0], LD, c->g.V, c->g.S, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LGF_OK;
@@ -827,15 +857,15 @@ int lgf_fft4d(lgf_ctx *c, double *fields, int sign) {
         // caller layout (stride V) -> work buffer (stride S), transform, natural order back
         HIPCHK(c, hipMemcpy2DAsync(W, S * sizeof(double2), F, row, row, 4,
                                    hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, launch_fft_xy<double>(c->g, W, -1, c->tw64, c->status, c->stream));
-        HIPCHK(c, launch_fft_zt<double>(c->g, W, -1, c->tw64, c->pt64, 0.0, c->zt64, c->status,
+        HIPCHK(c, launch_fft_xy<double>(c->g, W, -1, c->tw64, c->plan64, c->status, c->stream));
+        HIPCHK(c, launch_fft_zt<double>(c->g, W, -1, c->tw64, c->pt64, 0.0, c->plan64, c->status,
                                         c->stream));
         HIPCHK(c, launch_reorder_fields(c->g, W, S, F, V, 1, c->stream));
     } else {
         HIPCHK(c, launch_reorder_fields(c->g, F, V, W, S, 0, c->stream));
-        HIPCHK(c, launch_fft_zt<double>(c->g, W, +1, c->tw64, c->pt64, 0.0, c->zt64, c->status,
+        HIPCHK(c, launch_fft_zt<double>(c->g, W, +1, c->tw64, c->pt64, 0.0, c->plan64, c->status,
                                         c->stream));
-        HIPCHK(c, launch_fft_xy<double>(c->g, W, +1, c->tw64, c->status, c->stream));
+        HIPCHK(c, launch_fft_xy<double>(c->g, W, +1, c->tw64, c->plan64, c->status, c->stream));
         HIPCHK(c, hipMemcpy2DAsync(F, row, W, S * sizeof(double2), row, 4,
                                    hipMemcpyDeviceToDevice, c->stream));
     }

@@ -1,38 +1,50 @@
 // Mixed-radix FFT building blocks for the 4D lattice transforms.
 //
-// * dft<N, DIR>: an N-point DFT held entirely in registers, fully unrolled,
-//   by recursive decimation in time with radix-4/3/2 butterflies.  Twiddles
-//   come from one table tw[j] = exp(-2 pi i j / TW_M), TW_M = 1152 = 2^7 3^2,
-//   so every supported extent divides TW_M; the table is built on the host in
-//   long double.  DIR = -1: exp(-2 pi i n k / N) (forward), +1: inverse.
+// * Extents: every n = 2^a 3^b with 2 <= n <= FFT_MAX_EXTENT (256).
+// * dft<N, DIR, TL>: an N-point DFT held entirely in registers, fully
+//   unrolled, by recursive decimation in time with radix-4/3/2 butterflies.
+//   Twiddles come from the table of the lattice axis being transformed,
+//   tw[j] = exp(-2 pi i j / TL) for j < TL (TL = that axis's extent, which N
+//   divides), built on the host in long double.  DIR = -1:
+//   exp(-2 pi i n k / N) (forward), +1: inverse.
 // * lds_axis_fft: transforms every column of a tile held in LDS along one
 //   lattice axis.  Extents up to 32 take one register pass per column.  Larger
-//   extents N = N1*N2 take two in-place Stockham-like passes; the forward
-//   result is then stored in a permuted order (position p = k1*N2 + k2 holds
-//   frequency k1 + N1*k2) that the matching inverse takes back to natural
-//   order.  Whatever sits between forward and inverse (the momentum-space
-//   scaling) only needs each position's frequency, see fft_freq_of_pos.
+//   extents N = N1*N2 (N1 <= N2 <= 32, fft_split) take two in-place
+//   Stockham-like passes; the forward result is then stored in a permuted
+//   order (position p = k1*N2 + k2 holds frequency k1 + N1*k2) that the
+//   matching inverse takes back to natural order.  Whatever sits between
+//   forward and inverse (the momentum-space scaling) only needs each
+//   position's frequency, see fft_freq_of_pos.
 #pragma once
 #include "su3.hpp"
 
 namespace lgf {
 
-constexpr int TW_M = 1152;
+constexpr int FFT_MAX_EXTENT = 256;
 
+// N1 of the two-pass split of an extent n > 32: the largest divisor N1 with
+// N1 * N1 <= n and n / N1 <= 32 (the most balanced split into two register
+// transforms); 1 when n <= 32 or no such split exists.
 __host__ __device__ constexpr int fft_split(int n) {
-    // N1 for a two-pass transform of extent n > 32 (n = N1 * N2, N1 <= N2)
-    return n == 48 ? 6 : n == 64 ? 8 : n == 96 ? 8 : n == 128 ? 8 : 1;
+    int best = 1;
+    if (n > 32)
+        for (int d = 2; d * d <= n; ++d)
+            if (n % d == 0 && n / d <= 32) best = d;
+    return best;
 }
 
 // complex values one column transform of extent n keeps in registers at a
 // time: the whole column up to 32, else the larger factor of its split
 __host__ __device__ constexpr int fft_reg_span(int n) {
-    return n <= 32 ? n : (fft_split(n) > n / fft_split(n) ? fft_split(n) : n / fft_split(n));
+    return n <= 32 ? n : n / fft_split(n);
 }
 
 __host__ __device__ constexpr bool fft_supported(int n) {
-    return n == 2 || n == 3 || n == 4 || n == 6 || n == 8 || n == 12 || n == 16 || n == 24 ||
-           n == 32 || n == 48 || n == 64 || n == 96 || n == 128;
+    if (n < 2 || n > FFT_MAX_EXTENT) return false;
+    int m = n;
+    while (m % 2 == 0) m /= 2;
+    while (m % 3 == 0) m /= 3;
+    return m == 1 && (n <= 32 || fft_split(n) > 1);
 }
 
 // frequency held at position p after a forward transform of extent n
@@ -40,10 +52,11 @@ __host__ __device__ constexpr int fft_freq_of_pos(int n, int p) {
     return n <= 32 ? p : (p / (n / fft_split(n))) + fft_split(n) * (p % (n / fft_split(n)));
 }
 
-template <int N, int DIR, class T>
+template <int N, int DIR, class T, int TL>
 LGF_HD cpx<T> twiddle(const vec2_t<T> *__restrict__ tw, int k) {
-    // W_N^k = exp(DIR * 2 pi i k / N)
-    vec2_t<T> w = tw[((k % N) + N) % N * (TW_M / N)];
+    // W_N^k = exp(DIR * 2 pi i k / N) from the axis table of length TL
+    static_assert(TL % N == 0, "the transform length must divide the table length");
+    vec2_t<T> w = tw[((k % N) + N) % N * (TL / N)];
     return DIR < 0 ? mk<T>(w.x, w.y) : mk<T>(w.x, -w.y);
 }
 
@@ -74,7 +87,8 @@ template <int DIR, class T> LGF_HD void bfly4(cpx<T> *a) {
     a[3] = d02 - r;
 }
 
-template <int N, int DIR, class T> LGF_HD void dft(cpx<T> *a, const vec2_t<T> *__restrict__ tw) {
+template <int N, int DIR, int TL = N, class T>
+LGF_HD void dft(cpx<T> *a, const vec2_t<T> *__restrict__ tw) {
     if constexpr (N == 1) {
         return;
     } else if constexpr (N == 2) {
@@ -92,14 +106,14 @@ template <int N, int DIR, class T> LGF_HD void dft(cpx<T> *a, const vec2_t<T> *_
 #pragma unroll
             for (int m = 0; m < Q; ++m) b[p][m] = a[m * P + p];
 #pragma unroll
-        for (int p = 0; p < P; ++p) dft<Q, DIR>(b[p], tw);
+        for (int p = 0; p < P; ++p) dft<Q, DIR, TL>(b[p], tw);
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
             cpx<T> t[P];
             t[0] = b[0][k];
 #pragma unroll
             for (int p = 1; p < P; ++p)
-                t[p] = (k == 0) ? b[p][k] : cmul(b[p][k], twiddle<N, DIR, T>(tw, p * k));
+                t[p] = (k == 0) ? b[p][k] : cmul(b[p][k], twiddle<N, DIR, T, TL>(tw, p * k));
             if constexpr (P == 4) bfly4<DIR>(t);
             else if constexpr (P == 3) bfly3<DIR>(t);
             else bfly2<DIR>(t);
@@ -121,7 +135,7 @@ LGF_HD void lds_axis_fft_n(vec2_t<T> *lds, int ncols, int stride, Base base,
             cpx<T> a[N];
 #pragma unroll
             for (int j = 0; j < N; ++j) a[j] = ld<T>(lds + b0 + j * stride);
-            dft<N, DIR>(a, tw);
+            dft<N, DIR, N>(a, tw);
 #pragma unroll
             for (int j = 0; j < N; ++j) st<T>(lds + b0 + j * stride, a[j]);
         }
@@ -136,9 +150,9 @@ LGF_HD void lds_axis_fft_n(vec2_t<T> *lds, int ncols, int stride, Base base,
                 cpx<T> a[N1];
 #pragma unroll
                 for (int j = 0; j < N1; ++j) a[j] = ld<T>(lds + b0 + j * N2 * stride);
-                dft<N1, DIR>(a, tw);
+                dft<N1, DIR, N>(a, tw);
 #pragma unroll
-                for (int k1 = 1; k1 < N1; ++k1) a[k1] = cmul(a[k1], twiddle<N, DIR, T>(tw, n2 * k1));
+                for (int k1 = 1; k1 < N1; ++k1) a[k1] = cmul(a[k1], twiddle<N, DIR, T, N>(tw, n2 * k1));
 #pragma unroll
                 for (int j = 0; j < N1; ++j) st<T>(lds + b0 + j * N2 * stride, a[j]);
             }
@@ -150,7 +164,7 @@ LGF_HD void lds_axis_fft_n(vec2_t<T> *lds, int ncols, int stride, Base base,
                 cpx<T> a[N2];
 #pragma unroll
                 for (int j = 0; j < N2; ++j) a[j] = ld<T>(lds + b0 + j * stride);
-                dft<N2, DIR>(a, tw);
+                dft<N2, DIR, N>(a, tw);
 #pragma unroll
                 for (int j = 0; j < N2; ++j) st<T>(lds + b0 + j * stride, a[j]);
             }
@@ -162,9 +176,9 @@ LGF_HD void lds_axis_fft_n(vec2_t<T> *lds, int ncols, int stride, Base base,
                 cpx<T> a[N2];
 #pragma unroll
                 for (int j = 0; j < N2; ++j) a[j] = ld<T>(lds + b0 + j * stride);
-                dft<N2, DIR>(a, tw);
+                dft<N2, DIR, N>(a, tw);
 #pragma unroll
-                for (int n2 = 1; n2 < N2; ++n2) a[n2] = cmul(a[n2], twiddle<N, DIR, T>(tw, n2 * k1));
+                for (int n2 = 1; n2 < N2; ++n2) a[n2] = cmul(a[n2], twiddle<N, DIR, T, N>(tw, n2 * k1));
 #pragma unroll
                 for (int j = 0; j < N2; ++j) st<T>(lds + b0 + j * stride, a[j]);
             }
@@ -176,7 +190,7 @@ LGF_HD void lds_axis_fft_n(vec2_t<T> *lds, int ncols, int stride, Base base,
                 cpx<T> a[N1];
 #pragma unroll
                 for (int j = 0; j < N1; ++j) a[j] = ld<T>(lds + b0 + j * N2 * stride);
-                dft<N1, DIR>(a, tw);
+                dft<N1, DIR, N>(a, tw);
 #pragma unroll
                 for (int j = 0; j < N1; ++j) st<T>(lds + b0 + j * N2 * stride, a[j]);
             }
@@ -202,14 +216,14 @@ LGF_HD void lds_axis_fsi_n(vec2_t<T> *lds, int ncols, int stride, Base base, Pre
             cpx<T> a[N];
 #pragma unroll
             for (int j = 0; j < N; ++j) a[j] = ld<T>(lds + b0 + j * stride);
-            dft<N, -1>(a, tw);
+            dft<N, -1, N>(a, tw);
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 const T f = scale(info, k);
                 a[k].re *= f;
                 a[k].im *= f;
             }
-            dft<N, +1>(a, tw);
+            dft<N, +1, N>(a, tw);
 #pragma unroll
             for (int j = 0; j < N; ++j) st<T>(lds + b0 + j * stride, a[j]);
         }
@@ -223,9 +237,9 @@ LGF_HD void lds_axis_fsi_n(vec2_t<T> *lds, int ncols, int stride, Base base, Pre
             cpx<T> a[N1];
 #pragma unroll
             for (int j = 0; j < N1; ++j) a[j] = ld<T>(lds + b0 + j * N2 * stride);
-            dft<N1, -1>(a, tw);
+            dft<N1, -1, N>(a, tw);
 #pragma unroll
-            for (int k1 = 1; k1 < N1; ++k1) a[k1] = cmul(a[k1], twiddle<N, -1, T>(tw, n2 * k1));
+            for (int k1 = 1; k1 < N1; ++k1) a[k1] = cmul(a[k1], twiddle<N, -1, T, N>(tw, n2 * k1));
 #pragma unroll
             for (int j = 0; j < N1; ++j) st<T>(lds + b0 + j * N2 * stride, a[j]);
         }
@@ -239,16 +253,16 @@ LGF_HD void lds_axis_fsi_n(vec2_t<T> *lds, int ncols, int stride, Base base, Pre
             cpx<T> a[N2];
 #pragma unroll
             for (int j = 0; j < N2; ++j) a[j] = ld<T>(lds + b0 + j * stride);
-            dft<N2, -1>(a, tw);
+            dft<N2, -1, N>(a, tw);
 #pragma unroll
             for (int k2 = 0; k2 < N2; ++k2) {
                 const T f = scale(info, k1 * N2 + k2);
                 a[k2].re *= f;
                 a[k2].im *= f;
             }
-            dft<N2, +1>(a, tw);
+            dft<N2, +1, N>(a, tw);
 #pragma unroll
-            for (int n2 = 1; n2 < N2; ++n2) a[n2] = cmul(a[n2], twiddle<N, +1, T>(tw, n2 * k1));
+            for (int n2 = 1; n2 < N2; ++n2) a[n2] = cmul(a[n2], twiddle<N, +1, T, N>(tw, n2 * k1));
 #pragma unroll
             for (int j = 0; j < N2; ++j) st<T>(lds + b0 + j * stride, a[j]);
         }
@@ -260,12 +274,21 @@ LGF_HD void lds_axis_fsi_n(vec2_t<T> *lds, int ncols, int stride, Base base, Pre
             cpx<T> a[N1];
 #pragma unroll
             for (int j = 0; j < N1; ++j) a[j] = ld<T>(lds + b0 + j * N2 * stride);
-            dft<N1, +1>(a, tw);
+            dft<N1, +1, N>(a, tw);
 #pragma unroll
             for (int j = 0; j < N1; ++j) st<T>(lds + b0 + j * N2 * stride, a[j]);
         }
     }
 }
+
+// Every supported extent (fft_supported), as MACRO(n) for each.
+#define LGF_FFT_SMALL_EXTENTS(MACRO)                                                     \
+    MACRO(2) MACRO(3) MACRO(4) MACRO(6) MACRO(8) MACRO(9) MACRO(12) MACRO(16) MACRO(18)  \
+    MACRO(24) MACRO(27) MACRO(32)
+#define LGF_FFT_EXTENTS(MACRO)                                                           \
+    LGF_FFT_SMALL_EXTENTS(MACRO)                                                         \
+    MACRO(36) MACRO(48) MACRO(54) MACRO(64) MACRO(72) MACRO(81) MACRO(96) MACRO(108)     \
+    MACRO(128) MACRO(144) MACRO(162) MACRO(192) MACRO(216) MACRO(243) MACRO(256)
 
 template <class T, int RMAX, class Base, class Prep, class Scale>
 LGF_HD void lds_axis_fsi(int n, vec2_t<T> *lds, int ncols, int stride, Base base, Prep prep,
@@ -276,8 +299,7 @@ LGF_HD void lds_axis_fsi(int n, vec2_t<T> *lds, int ncols, int stride, Base base
         if constexpr (fft_reg_span(NN) <= RMAX)                                        \
             lds_axis_fsi_n<NN, T>(lds, ncols, stride, base, prep, scale, tw);          \
         break;
-        LGF_CASE(2) LGF_CASE(3) LGF_CASE(4) LGF_CASE(6) LGF_CASE(8) LGF_CASE(12) LGF_CASE(16)
-        LGF_CASE(24) LGF_CASE(32) LGF_CASE(48) LGF_CASE(64) LGF_CASE(96) LGF_CASE(128)
+        LGF_FFT_EXTENTS(LGF_CASE)
 #undef LGF_CASE
     default: break;
     }
@@ -295,8 +317,7 @@ LGF_HD void lds_axis_fft(int n, vec2_t<T> *lds, int ncols, int stride, Base base
         if constexpr (fft_reg_span(NN) <= RMAX)                                        \
             lds_axis_fft_n<NN, DIR, T>(lds, ncols, stride, base, tw);                  \
         break;
-        LGF_CASE(2) LGF_CASE(3) LGF_CASE(4) LGF_CASE(6) LGF_CASE(8) LGF_CASE(12) LGF_CASE(16)
-        LGF_CASE(24) LGF_CASE(32) LGF_CASE(48) LGF_CASE(64) LGF_CASE(96) LGF_CASE(128)
+        LGF_FFT_EXTENTS(LGF_CASE)
 #undef LGF_CASE
     default: break;
     }

@@ -4,8 +4,13 @@
 //   k_fft_xy_rc / k_fft_zt_rc  one axis held in registers, the other
 //                              exchanged through LDS (extents <= 32)
 //   k_fft_xy                   a whole (x,y) plane in LDS (larger extents)
-//   k_fft_axis                 one axis of the (z,t) plane per pass, W sites
-//                              x the axis x B slices in LDS (larger extents)
+//   k_fft_axis                 one axis per pass: W inner sites x the axis x B
+//                              slices in LDS (whatever the other two schemes
+//                              cannot hold)
+//
+// Twiddles: `tw` is the context's table buffer holding the axis tables of x,
+// y, z and t one after the other (Lx, Ly, Lz and Lt entries); a transform
+// along an axis reads only that axis's table.
 #pragma once
 #include <type_traits>
 
@@ -14,6 +19,31 @@
 namespace lgf {
 
 static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// Every listed extent is supported and every supported extent is listed.
+#define LGF_COUNT_ONE(n) +1
+#define LGF_AND_SUPPORTED(n) &&fft_supported(n)
+constexpr int fft_count_supported() {
+    int c = 0;
+    for (int n = 2; n <= FFT_MAX_EXTENT; ++n)
+        if (fft_supported(n)) ++c;
+    return c;
+}
+static_assert(fft_count_supported() == 0 LGF_FFT_EXTENTS(LGF_COUNT_ONE), "extent list");
+static_assert(true LGF_FFT_EXTENTS(LGF_AND_SUPPORTED), "extent list");
+#undef LGF_COUNT_ONE
+#undef LGF_AND_SUPPORTED
+
+// axis tables inside the table buffer
+template <class T> __host__ __device__ inline const vec2_t<T> *tw_y(const geom &g, const vec2_t<T> *tw) {
+    return tw + g.Lx;
+}
+template <class T> __host__ __device__ inline const vec2_t<T> *tw_z(const geom &g, const vec2_t<T> *tw) {
+    return tw + g.Lx + g.Ly;
+}
+template <class T> __host__ __device__ inline const vec2_t<T> *tw_t(const geom &g, const vec2_t<T> *tw) {
+    return tw + g.Lx + g.Ly + g.Lz;
+}
 
 // 1/x from the hardware estimate refined by Newton steps (to about 1 ulp).
 __device__ __forceinline__ double recip(double x) {
@@ -40,6 +70,9 @@ __device__ __forceinline__ T fa_factor(T base, T pz, T p2max_over_V) {
 // ---------------------------------------------------------------------------
 
 constexpr int XY_BLOCK = 256;
+// a whole (x,y) plane of one field in LDS up to this size; larger planes take
+// an x pass and a y pass
+constexpr size_t XY_PLANE_LDS_MAX = 160 * 1024;
 
 // RMAX: largest register span (fft_reg_span) of the extents this instance handles
 template <class T, int DIR, int RMAX>
@@ -51,6 +84,7 @@ __global__ void __launch_bounds__(XY_BLOCK)
     vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
     const int Lx = g.Lx, Ly = g.Ly, P = Lx + 1;
     const long Lxy = (long)Lx * Ly;
+    const vec2_t<T> *twx = tw, *twy = tw_y<T>(g, tw);
     vec2_t<T> *plane = D + (long)blockIdx.y * g.S + (long)blockIdx.x * Lxy;
     for (int i = threadIdx.x; i < Lxy; i += XY_BLOCK) {
         const int y = i / Lx, x = i - y * Lx;
@@ -60,13 +94,13 @@ __global__ void __launch_bounds__(XY_BLOCK)
     auto rows = [P](int c) { return c * P; };
     auto cols = [](int c) { return c; };
     if (DIR < 0) {
-        lds_axis_fft<DIR, T, RMAX>(Lx, lds, Ly, 1, rows, tw);
+        lds_axis_fft<DIR, T, RMAX>(Lx, lds, Ly, 1, rows, twx);
         __syncthreads();
-        lds_axis_fft<DIR, T, RMAX>(Ly, lds, Lx, P, cols, tw);
+        lds_axis_fft<DIR, T, RMAX>(Ly, lds, Lx, P, cols, twy);
     } else {
-        lds_axis_fft<DIR, T, RMAX>(Ly, lds, Lx, P, cols, tw);
+        lds_axis_fft<DIR, T, RMAX>(Ly, lds, Lx, P, cols, twy);
         __syncthreads();
-        lds_axis_fft<DIR, T, RMAX>(Lx, lds, Ly, 1, rows, tw);
+        lds_axis_fft<DIR, T, RMAX>(Lx, lds, Ly, 1, rows, twx);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < Lxy; i += XY_BLOCK) {
@@ -99,7 +133,7 @@ __global__ void __launch_bounds__(XY_BLOCK)
     __syncthreads();
     auto cols = [Lx, REG](int cc) { return (cc / Lx) * REG + (cc % Lx); };      // cc = x + Lx f
     auto rows = [Ly, REG, P](int cc) { return (cc / Ly) * REG + (cc % Ly) * P; };  // cc = y + Ly f
-    lds_axis_fft<+1, T, RMAX>(Ly, lds, 4 * Lx, P, cols, tw);
+    lds_axis_fft<+1, T, RMAX>(Ly, lds, 4 * Lx, P, cols, tw_y<T>(g, tw));
     __syncthreads();
     lds_axis_fft<+1, T, RMAX>(Lx, lds, 4 * Ly, 1, rows, tw);
     __syncthreads();
@@ -112,73 +146,75 @@ __global__ void __launch_bounds__(XY_BLOCK)
 }
 
 // ---------------------------------------------------------------------------
-// One-axis passes for (z, t) planes too large for a register column (an
-// extent above 32): the (z,t) transform becomes three passes over the field,
-// z forward, then t forward / scaling / t inverse, then z inverse.  A block
-// holds W consecutive xy-sites (rows of up to 1 KB) x the whole axis x B
-// slices of the other axis, so every load and store is a coalesced row;
-// the transform of each column runs in LDS (lds_axis_fft, one or two passes).
-// LDS element (w, j, b) at b*N*PW + j*PW + w, PW = W + 1.
-// AX = 2: the z axis (slices along t); AX = 3: the t axis (slices along z).
+// One-axis passes (axis_plan): for (z,t) planes too large for a register
+// column (an extent above 32) the (z,t) transform becomes three passes over
+// the field, z forward, then t forward / scaling / t inverse, then z inverse;
+// (x,y) planes too large for LDS take an x pass and a y pass.  A block holds
+// W inner elements (rows of up to 1 KB) x the whole axis x B slices, so every
+// load and store is a contiguous row; the transform of each column runs in
+// LDS (lds_axis_fft, one or two passes).
 // MODE -1 forward, +1 inverse, 0 (t axis only) forward, times p2max/(V p2),
 // inverse.
 // ---------------------------------------------------------------------------
 
 constexpr int AXIS_BLOCK = 256;
 constexpr int ZT_PAD = 4;
+// 32 KB tiles let four blocks share a compute unit (the register limit of
+// these kernels); 64 KB tiles, with wider rows but three blocks, took 15-25%
+// longer at 48^3 x 96.
+constexpr size_t AXIS_TILE_BYTES = 32 * 1024;
 
 // Register budgets: 128 VGPRs for spans up to 16 (four waves per SIMD, the
 // occupancy the 32 KB tiles allow; the fused scaled round trip would take
 // 129), 256 for the wider spans (without the hint it spills to AGPRs).
-template <class T, int AX, int MODE, int RMAX>
+template <class T, int MODE, int RMAX>
 __global__ void __launch_bounds__(AXIS_BLOCK) __attribute__((amdgpu_waves_per_eu(RMAX <= 16 ? 4 : 2)))
-    k_fft_axis(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
-               const T *__restrict__ ptab, T p2max_over_V, int W, int B,
+    k_fft_axis(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ twa,
+               const T *__restrict__ ptab, T p2max_over_V, axis_plan ap,
                const dev_status *__restrict__ status) {
     if (status->done) return;
     extern __shared__ unsigned char smem_raw[];
     vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
-    const int Lz = g.Lz, N = AX == 2 ? g.Lz : g.Lt;
-    const long Lxy = (long)g.Lx * g.Ly;
+    const int N = ap.N, W = ap.W, PW = ap.PW, PB = ap.PB;
     const long s0 = (long)xcd_block(blockIdx.x, gridDim.x) * W;
-    const int Wt = (int)min((long)W, Lxy - s0);
-    const int o0 = blockIdx.y * B;  // first slice of the other axis
-    const int PW = W + 1, PB = N * PW;
-    vec2_t<T> *F = D + (long)blockIdx.z * g.S + s0;
-    // (z, t) plane index of element (j, b)
-    auto zt = [=](int j, int b) { return AX == 2 ? (o0 + b) * Lz + j : j * Lz + (o0 + b); };
-    const int nel = W * N * B;
+    const int Wt = (int)min((long)W, ap.R - s0);
+    const int o0 = blockIdx.y * ap.B;  // first slice
+    const int Bt = min(ap.B, ap.nslice - o0);
+    vec2_t<T> *F = D + (long)blockIdx.z * g.S + s0 + (long)o0 * ap.sb;
+    const int nel = W * N * ap.B;
     for (int i = threadIdx.x; i < nel; i += AXIS_BLOCK) {
         const int w = i % W, r = i / W, j = r % N, b = r / N;
         vec2_t<T> v;
         v.x = 0;
         v.y = 0;
-        if (w < Wt) v = F[(long)zt(j, b) * Lxy + w];
+        if (w < Wt && b < Bt) v = F[(long)j * ap.sj + (long)b * ap.sb + w];
         lds[b * PB + j * PW + w] = v;
     }
     __syncthreads();
-    auto col = [W, PW, PB](int c) { return (c / W) * PB + (c % W); };  // c = w + W*b
+    auto col = [W, PB](int c) { return (c / W) * PB + (c % W); };  // c = w + W*b
     if (MODE == 0) {
+        // the t axis: inner elements are xy-sites, slices are z
         const T *px = ptab, *py = ptab + g.Lx, *pz = ptab + g.Lx + g.Ly,
                 *pt = ptab + g.Lx + g.Ly + g.Lz;
+        const long Lxy = (long)g.Lx * g.Ly;
         // per column c = w + W*b: its p2 without the t term, or -1 for a
         // padding column of a ragged tile (factor 0)
         auto prep = [=](int c) -> T {
             const int w = c % W, b = c / W;
             const long sxy = s0 + w;
-            if (sxy >= Lxy) return T(-1);
+            if (sxy >= Lxy || b >= Bt) return T(-1);
             const int y = (int)(sxy / g.Lx), x = (int)(sxy - (long)y * g.Lx);
             return (px[x] + py[y]) + pz[o0 + b];
         };
         auto scale = [=](T base, int j) -> T { return fa_factor<T>(base, pt[j], p2max_over_V); };
-        lds_axis_fsi<T, RMAX>(N, lds, W * B, PW, col, prep, scale, tw);
+        lds_axis_fsi<T, RMAX>(N, lds, W * ap.B, PW, col, prep, scale, twa);
     } else {
-        lds_axis_fft<MODE, T, RMAX>(N, lds, W * B, PW, col, tw);
+        lds_axis_fft<MODE, T, RMAX>(N, lds, W * ap.B, PW, col, twa);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nel; i += AXIS_BLOCK) {
         const int w = i % W, r = i / W, j = r % N, b = r / N;
-        if (w < Wt) F[(long)zt(j, b) * Lxy + w] = lds[b * PB + j * PW + w];
+        if (w < Wt && b < Bt) F[(long)j * ap.sj + (long)b * ap.sb + w] = lds[b * PB + j * PW + w];
     }
 }
 
@@ -237,8 +273,7 @@ __device__ __forceinline__ void col_fwd_scale_inv(int n, vec2_t<T> *lds, int nco
     switch (n) {
 #define LGF_SCASE(NN) \
     case NN: col_fwd_scale_inv_n<NN, T>(lds, ncols, stride, base, prep, scale, tw); break;
-        LGF_SCASE(2) LGF_SCASE(3) LGF_SCASE(4) LGF_SCASE(6) LGF_SCASE(8) LGF_SCASE(12)
-        LGF_SCASE(16) LGF_SCASE(24) LGF_SCASE(32)
+        LGF_FFT_SMALL_EXTENTS(LGF_SCASE)
 #undef LGF_SCASE
     default: break;
     }
@@ -251,8 +286,7 @@ __device__ __forceinline__ void col_fft_small(int n, vec2_t<T> *lds, int ncols, 
     switch (n) {
 #define LGF_CCASE(NN) \
     case NN: lds_axis_fft_n<NN, DIR, T>(lds, ncols, stride, base, tw); break;
-        LGF_CCASE(2) LGF_CCASE(3) LGF_CCASE(4) LGF_CCASE(6) LGF_CCASE(8) LGF_CCASE(12)
-        LGF_CCASE(16) LGF_CCASE(24) LGF_CCASE(32)
+        LGF_FFT_SMALL_EXTENTS(LGF_CCASE)
 #undef LGF_CCASE
     default: break;
     }
@@ -273,6 +307,7 @@ __global__ void __launch_bounds__(rc_max_threads<T>())
     const int x = threadIdx.x % Lx, fl = threadIdx.x / Lx;
     const int f = blockIdx.y * F + fl;
     const int SW = Lx + 1, PJ = F * SW;
+    const vec2_t<T> *twy = tw_y<T>(g, tw);
     vec2_t<T> *p = D + (long)f * g.S + (long)blockIdx.x * Lxy + x;
     cpx<T> a[NY];
 #pragma unroll
@@ -280,11 +315,11 @@ __global__ void __launch_bounds__(rc_max_threads<T>())
     auto base = [F, SW, PJ](int c) { return (c / F) * PJ + (c % F) * SW; };  // c = fl + F*j
     auto col = [&](int, int C) { col_fft_small<DIR, T>(Lx, lds, F * C, 1, base, tw); };
     if (DIR < 0) {
-        dft<NY, -1>(a, tw);
+        dft<NY, -1>(a, twy);
         exchange_axis<NY, T>(a, fl, x, 1, SW, PJ, lds, col);
     } else {
         exchange_axis<NY, T>(a, fl, x, 1, SW, PJ, lds, col);
-        dft<NY, +1>(a, tw);
+        dft<NY, +1>(a, twy);
     }
 #pragma unroll
     for (int y = 0; y < NY; ++y) st<T>(p + (long)y * Lx, a[y]);
@@ -316,7 +351,7 @@ __global__ void __launch_bounds__(rc_max_threads<T>())
     auto base = [SW, PJ](int cc) { return (cc / F) * PJ + (cc % F) * SW; };  // cc = fl + F*j
     auto col = [&](int, int C) { col_fft_small<+1, T>(Lx, lds, F * C, 1, base, tw); };
     exchange_axis<NY, T>(a, fl, x, 1, SW, PJ, lds, col);
-    dft<NY, +1>(a, tw);
+    dft<NY, +1>(a, tw_y<T>(g, tw));
     __syncthreads();  // every thread has read its column back
 #pragma unroll
     for (int y = 0; y < NY; ++y) st<T>(lds + y * PJ + fl * SW + x, a[y]);
@@ -345,6 +380,7 @@ __global__ void __launch_bounds__(rc_max_threads<T>())
     const int w = threadIdx.x % W, z = threadIdx.x / W;
     const long s0 = (long)xcd_block(blockIdx.x, gridDim.x) * W;
     const bool live = s0 + w < Lxy;
+    const vec2_t<T> *twz = tw_z<T>(g, tw), *twt = tw_t<T>(g, tw);
     vec2_t<T> *p = D + (long)blockIdx.y * g.S + (long)z * Lxy + s0 + w;
     const long tstride = (long)Lz * Lxy;
     cpx<T> a[NT];
@@ -352,7 +388,7 @@ __global__ void __launch_bounds__(rc_max_threads<T>())
     for (int t = 0; t < NT; ++t) a[t] = live ? ld<T>(p + t * tstride) : mk<T>(0, 0);
     const int PJ = Lz * W + ZT_PAD;
     auto base = [W, PJ](int c) { return (c / W) * PJ + (c % W); };  // c = w + W*j
-    if (MODE <= 0) dft<NT, -1>(a, tw);
+    if (MODE <= 0) dft<NT, -1>(a, twt);
     if (MODE == 0) {
         const T *px = ptab, *py = ptab + g.Lx, *pz = ptab + g.Lx + g.Ly,
                 *pt = ptab + g.Lx + g.Ly + g.Lz;
@@ -366,22 +402,23 @@ __global__ void __launch_bounds__(rc_max_threads<T>())
                 return (px[x] + py[y]) + pt[c0 + c / W];
             };
             auto scale = [=](T base, int k) -> T { return fa_factor<T>(base, pz[k], p2max_over_V); };
-            col_fwd_scale_inv<T>(Lz, lds, W * C, W, base, prep, scale, tw);
+            col_fwd_scale_inv<T>(Lz, lds, W * C, W, base, prep, scale, twz);
         };
         exchange_axis<NT, T>(a, w, z, W, 1, PJ, lds, col);
     } else {
-        auto col = [&](int, int C) { col_fft_small<MODE, T>(Lz, lds, W * C, W, base, tw); };
+        auto col = [&](int, int C) { col_fft_small<MODE, T>(Lz, lds, W * C, W, base, twz); };
         exchange_axis<NT, T>(a, w, z, W, 1, PJ, lds, col);
     }
-    if (MODE >= 0) dft<NT, +1>(a, tw);
+    if (MODE >= 0) dft<NT, +1>(a, twt);
     if (live) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) st<T>(p + t * tstride, a[t]);
     }
 }
 
-#define LGF_NA_CASES(MACRO)                                                        \
-    MACRO(2) MACRO(3) MACRO(4) MACRO(6) MACRO(8) MACRO(12) MACRO(16) MACRO(24) MACRO(32)
+// ---------------------------------------------------------------------------
+// planning and launchers
+// ---------------------------------------------------------------------------
 
 template <class T> inline int xy_fields_per_block(const geom &g) {
     int F = g.nf;
@@ -389,69 +426,226 @@ template <class T> inline int xy_fields_per_block(const geom &g) {
     return F;
 }
 
-template <class T> inline bool xy_use_rc(const geom &g) { return g.Ly <= 32 && g.Lx <= 32; }
+// A one-axis pass over axis ax: rows of up to 1 KB (W consecutive inner
+// elements; one element for the x axis), then as many slices as keep a tile
+// within AXIS_TILE_BYTES.
+template <class T> axis_plan plan_axis(const geom &g, int ax) {
+    const int L[4] = {g.Lx, g.Ly, g.Lz, g.Lt};
+    const long Lxy = (long)g.Lx * g.Ly;
+    axis_plan a;
+    a.N = L[ax];
+    if (ax == 0) {
+        a.R = 1;
+        a.sj = 1;
+        a.sb = g.Lx;
+        a.nslice = g.Ly * g.Lz * g.Lt;
+    } else if (ax == 1) {
+        a.R = g.Lx;
+        a.sj = g.Lx;
+        a.sb = Lxy;
+        a.nslice = g.Lz * g.Lt;
+    } else if (ax == 2) {
+        a.R = Lxy;
+        a.sj = Lxy;
+        a.sb = Lxy * g.Lz;
+        a.nslice = g.Lt;
+    } else {  // t: inner xy-sites, slices along z
+        a.R = Lxy;
+        a.sj = Lxy * g.Lz;
+        a.sb = Lxy;
+        a.nslice = g.Lz;
+    }
+    const size_t e = sizeof(vec2_t<T>);
+    auto strides = [&](int w, int b, int &pw, int &pb) {
+        pw = w == 1 ? 1 : w + 1;
+        pb = a.N * pw;
+        if (w == 1 && pb % 2 == 0) ++pb;  // columns of consecutive threads on odd strides
+        return (size_t)b * pb * e;
+    };
+    int pw, pb;
+    int w = (int)(1024 / e);
+    while (w > 1 && (w > a.R || strides(w, 1, pw, pb) > AXIS_TILE_BYTES)) w >>= 1;
+    // slices: a power of two dividing the slice count, at most 8 with rows
+    // (64 for the x axis, whose rows are single elements)
+    int b = a.R == 1 ? 64 : 8;
+    while (b > 1 && (strides(w, b, pw, pb) > AXIS_TILE_BYTES || a.nslice % b != 0)) b >>= 1;
+    a.W = w;
+    a.B = b;
+    a.lds = strides(w, b, pw, pb);
+    a.PW = pw;
+    a.PB = pb;
+    return a;
+}
 
-template <class T> size_t fft_xy_lds_bytes(const geom &g) {
-    if (xy_use_rc<T>(g))
-        return (size_t)g.Ly * xy_fields_per_block<T>(g) * (g.Lx + 1) * sizeof(vec2_t<T>);
-    return (size_t)g.Ly * (g.Lx + 1) * sizeof(vec2_t<T>);
+template <class T> fft_plan plan_fft(const geom &g, size_t zt_lds_budget) {
+    fft_plan p{};
+    const size_t e = sizeof(vec2_t<T>);
+    if (g.Lx <= 32 && g.Ly <= 32) {
+        p.xy = 0;
+        p.lds_xy = (size_t)g.Ly * xy_fields_per_block<T>(g) * (g.Lx + 1) * e;
+    } else if ((size_t)g.Ly * (g.Lx + 1) * e <= XY_PLANE_LDS_MAX) {
+        p.xy = 1;
+        p.lds_xy = (size_t)g.Ly * (g.Lx + 1) * e;
+    } else {
+        p.xy = 2;
+        p.x = plan_axis<T>(g, 0);
+        p.y = plan_axis<T>(g, 1);
+    }
+    // (z,t): register-column kernel when both extents are at most 32 (tile of
+    // W sites with 128-byte rows), else the z and t passes
+    const long Lxy = (long)g.Lx * g.Ly;
+    if (g.Lt <= 32 && g.Lz <= 32) {
+        auto rc_bytes = [&](int w) { return (size_t)g.Lt * ((size_t)g.Lz * w + ZT_PAD) * e; };
+        int W = 128 / (int)e;
+        while (W > 1 && (W * g.Lz > rc_max_threads<T>() || W > Lxy || rc_bytes(W) > zt_lds_budget))
+            W >>= 1;
+        if (W * g.Lz <= rc_max_threads<T>() && rc_bytes(W) <= 160 * 1024) {
+            p.rc = true;
+            p.W = W;
+            p.lds = rc_bytes(W);
+            return p;
+        }
+    }
+    p.rc = false;
+    p.z = plan_axis<T>(g, 2);
+    p.t = plan_axis<T>(g, 3);
+    p.W = p.z.W;
+    p.lds = std::max(p.z.lds, p.t.lds);
+    return p;
+}
+
+inline dim3 axis_grid(const axis_plan &a, int nf) {
+    return dim3(nblk(a.R, a.W), nblk(a.nslice, a.B), (unsigned)nf);
+}
+
+template <class T> void fft_set_max_lds(const geom &g, const fft_plan &p) {
+    auto set = [](const void *f, size_t b) {
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+    };
+    if (p.rc) {
+#define LGF_ZTA(NN)                                                                 \
+    case NN:                                                                        \
+        set(reinterpret_cast<const void *>(&k_fft_zt_rc<T, NN, 0>), p.lds);        \
+        set(reinterpret_cast<const void *>(&k_fft_zt_rc<T, NN, -1>), p.lds);       \
+        set(reinterpret_cast<const void *>(&k_fft_zt_rc<T, NN, 1>), p.lds);        \
+        break;
+        switch (g.Lt) {
+            LGF_FFT_SMALL_EXTENTS(LGF_ZTA)
+        default: break;
+        }
+#undef LGF_ZTA
+    }
+    size_t ax = 0;
+    if (!p.rc) ax = std::max(p.z.lds, p.t.lds);
+    if (p.xy == 2) ax = std::max(ax, std::max(p.x.lds, p.y.lds));
+    if (ax > 0) {
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, -1, 16>), ax);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 1, 16>), ax);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 0, 16>), ax);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, -1, 32>), ax);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 1, 32>), ax);
+        set(reinterpret_cast<const void *>(&k_fft_axis<T, 0, 32>), ax);
+    }
+    if constexpr (std::is_same<T, float>::value) {
+        if (p.xy == 1 && xy_acc_fusable<T>(g, p)) {
+            const size_t b = (size_t)4 * g.Ly * (g.Lx + 1) * sizeof(vec2_t<T>);
+            set(reinterpret_cast<const void *>(&k_fft_xy_acc<T, 16, true>), b);
+            set(reinterpret_cast<const void *>(&k_fft_xy_acc<T, 16, false>), b);
+            set(reinterpret_cast<const void *>(&k_fft_xy_acc<T, 32, true>), b);
+            set(reinterpret_cast<const void *>(&k_fft_xy_acc<T, 32, false>), b);
+        }
+    }
+    if (p.xy == 1) {
+        set(reinterpret_cast<const void *>(&k_fft_xy<T, -1, 16>), p.lds_xy);
+        set(reinterpret_cast<const void *>(&k_fft_xy<T, 1, 16>), p.lds_xy);
+        set(reinterpret_cast<const void *>(&k_fft_xy<T, -1, 32>), p.lds_xy);
+        set(reinterpret_cast<const void *>(&k_fft_xy<T, 1, 32>), p.lds_xy);
+    }
+}
+
+// One one-axis pass (the instance for the axis extent's register span).
+template <class T, int MODE>
+hipError_t launch_axis(const geom &g, vec2_t<T> *D, const vec2_t<T> *twa, const T *ptab,
+                       T p2max_over_V, const axis_plan &a, const dev_status *status,
+                       hipStream_t st) {
+    const dim3 grid = axis_grid(a, g.nf);
+    if (fft_reg_span(a.N) <= 16)
+        k_fft_axis<T, MODE, 16><<<grid, AXIS_BLOCK, a.lds, st>>>(g, D, twa, ptab, p2max_over_V, a,
+                                                                 status);
+    else
+        k_fft_axis<T, MODE, 32><<<grid, AXIS_BLOCK, a.lds, st>>>(g, D, twa, ptab, p2max_over_V, a,
+                                                                 status);
+    return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const dev_status *status,
-                         hipStream_t st) {
+hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const fft_plan &pl,
+                         const dev_status *status, hipStream_t st) {
     auto Dp = static_cast<vec2_t<T> *>(D);
     auto twp = static_cast<const vec2_t<T> *>(tw);
-    const size_t lds = fft_xy_lds_bytes<T>(g);
-    if (xy_use_rc<T>(g)) {
+    if (pl.xy == 0) {
         const int F = xy_fields_per_block<T>(g);
         dim3 grid((unsigned)(g.Lz * g.Lt), (unsigned)(g.nf / F));
         const unsigned nt = (unsigned)(F * g.Lx);
+        const size_t lds = pl.lds_xy;
 #define LGF_XY(NN)                                                                            \
     case NN:                                                                                  \
         if (dir < 0) k_fft_xy_rc<T, NN, -1><<<grid, nt, lds, st>>>(g, Dp, twp, F, status);   \
         else k_fft_xy_rc<T, NN, 1><<<grid, nt, lds, st>>>(g, Dp, twp, F, status);            \
         break;
         switch (g.Ly) {
-            LGF_NA_CASES(LGF_XY)
+            LGF_FFT_SMALL_EXTENTS(LGF_XY)
         default: return hipErrorInvalidValue;
         }
 #undef LGF_XY
         return hipGetLastError();
     }
+    if (pl.xy == 2) {
+        // separate passes: x then y forward, y then x inverse
+        hipError_t e;
+        const T zero = T(0);
+        if (dir < 0) {
+            if ((e = launch_axis<T, -1>(g, Dp, twp, nullptr, zero, pl.x, status, st))) return e;
+            return launch_axis<T, -1>(g, Dp, tw_y<T>(g, twp), nullptr, zero, pl.y, status, st);
+        }
+        if ((e = launch_axis<T, 1>(g, Dp, tw_y<T>(g, twp), nullptr, zero, pl.y, status, st)))
+            return e;
+        return launch_axis<T, 1>(g, Dp, twp, nullptr, zero, pl.x, status, st);
+    }
     dim3 grid((unsigned)(g.Lz * g.Lt), (unsigned)g.nf);
     if (fft_reg_span(g.Lx) <= 16 && fft_reg_span(g.Ly) <= 16) {
-        if (dir < 0) k_fft_xy<T, -1, 16><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
-        else k_fft_xy<T, +1, 16><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
+        if (dir < 0) k_fft_xy<T, -1, 16><<<grid, XY_BLOCK, pl.lds_xy, st>>>(g, Dp, twp, status);
+        else k_fft_xy<T, +1, 16><<<grid, XY_BLOCK, pl.lds_xy, st>>>(g, Dp, twp, status);
     } else {
-        if (dir < 0) k_fft_xy<T, -1, 32><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
-        else k_fft_xy<T, +1, 32><<<grid, XY_BLOCK, lds, st>>>(g, Dp, twp, status);
+        if (dir < 0) k_fft_xy<T, -1, 32><<<grid, XY_BLOCK, pl.lds_xy, st>>>(g, Dp, twp, status);
+        else k_fft_xy<T, +1, 32><<<grid, XY_BLOCK, pl.lds_xy, st>>>(g, Dp, twp, status);
     }
     return hipGetLastError();
 }
 
 // The fused inverse (x,y) pass with G accumulation: register-column planes
-// holding all 4 fields in one block.
+// holding all 4 fields in one block, or whole planes of all 4 fields in LDS.
 constexpr size_t XY_ACC_LDS_MAX = 150 * 1024;
 template <class T> inline size_t xy_acc_lds_bytes(const geom &g) {
     return (size_t)4 * g.Ly * (g.Lx + 1) * sizeof(vec2_t<T>);
 }
-template <class T> inline bool xy_acc_fusable(const geom &g) {
+template <class T> bool xy_acc_fusable(const geom &g, const fft_plan &pl) {
     if (g.nc != 3 || g.nf != 4) return false;
-    if (xy_use_rc<T>(g)) return xy_fields_per_block<T>(g) == 4;
-    return xy_acc_lds_bytes<T>(g) <= XY_ACC_LDS_MAX;
+    if (pl.xy == 0) return xy_fields_per_block<T>(g) == 4;
+    if (pl.xy == 1) return xy_acc_lds_bytes<T>(g) <= XY_ACC_LDS_MAX;
+    return false;
 }
 
 template <class T>
-hipError_t launch_fft_xy_inv_acc(const geom &g, void *D, const void *tw, const void *Gold,
-                                 void *Gnew, double c, bool exact, const dev_status *status,
-                                 hipStream_t st) {
-    if (!xy_acc_fusable<T>(g)) return hipErrorInvalidValue;
+hipError_t launch_fft_xy_inv_acc(const geom &g, void *D, const void *tw, const fft_plan &pl,
+                                 const void *Gold, void *Gnew, double c, bool exact,
+                                 const dev_status *status, hipStream_t st) {
+    if (!xy_acc_fusable<T>(g, pl)) return hipErrorInvalidValue;
     auto Dp = static_cast<const vec2_t<T> *>(D);
     auto twp = static_cast<const vec2_t<T> *>(tw);
     auto Go = static_cast<const vec2_t<T> *>(Gold);
     auto Gn = static_cast<vec2_t<T> *>(Gnew);
-    if (!xy_use_rc<T>(g)) {
+    if (pl.xy == 1) {
         const size_t b = xy_acc_lds_bytes<T>(g);
         const dim3 grid((unsigned)(g.Lz * g.Lt));
         const bool sm = fft_reg_span(g.Lx) <= 16 && fft_reg_span(g.Ly) <= 16;
@@ -466,7 +660,7 @@ hipError_t launch_fft_xy_inv_acc(const geom &g, void *D, const void *tw, const v
 #undef LGF_XG
         return hipGetLastError();
     }
-    const size_t lds = fft_xy_lds_bytes<T>(g);
+    const size_t lds = pl.lds_xy;
     const dim3 grid((unsigned)(g.Lz * g.Lt));
     const unsigned nt = (unsigned)(4 * g.Lx);
 #define LGF_XA(NN)                                                                            \
@@ -477,117 +671,23 @@ hipError_t launch_fft_xy_inv_acc(const geom &g, void *D, const void *tw, const v
             k_fft_xy_rc_acc<T, NN, false><<<grid, nt, lds, st>>>(g, Dp, twp, Go, Gn, c, status); \
         break;
     switch (g.Ly) {
-        LGF_NA_CASES(LGF_XA)
+        LGF_FFT_SMALL_EXTENTS(LGF_XA)
     default: return hipErrorInvalidValue;
     }
 #undef LGF_XA
     return hipGetLastError();
 }
 
-// (z,t) plan: register-column kernel when Lt <= 32 (tile of W sites with
-// 128-byte rows), else the LDS-tile kernel with the widest W that fits.
-template <class T> zt_plan plan_zt(const geom &g, size_t lds_budget) {
-    zt_plan p{};
-    const long Lxy = (long)g.Lx * g.Ly;
-    if (g.Lt <= 32 && g.Lz <= 32) {
-        auto rc_bytes = [&](int w) {
-            return (size_t)g.Lt * ((size_t)g.Lz * w + ZT_PAD) * sizeof(vec2_t<T>);
-        };
-        int W = 128 / (int)sizeof(vec2_t<T>);
-        while (W > 1 && (W * g.Lz > rc_max_threads<T>() || W > Lxy || rc_bytes(W) > lds_budget))
-            W >>= 1;
-        if (W * g.Lz <= rc_max_threads<T>() && rc_bytes(W) <= 160 * 1024) {
-            p.rc = true;
-            p.W = W;
-            p.lds = rc_bytes(W);
-            return p;
-        }
-    }
-    // one-axis passes: rows of up to 1 KB (W consecutive sites), then as many
-    // slices of the other axis as keep a tile within AXIS_TILE_BYTES, dividing
-    // its extent.  32 KB tiles let four blocks share a compute unit (the
-    // register limit of these kernels); 64 KB tiles, with wider rows but three
-    // blocks, took 15-25% longer at 48^3 x 96.
-    constexpr size_t AXIS_TILE_BYTES = 32 * 1024;
-    auto tile = [&](int n, int w, int b) { return (size_t)b * n * (w + 1) * sizeof(vec2_t<T>); };
-    auto width = [&](int n) {
-        int w = 1024 / (int)sizeof(vec2_t<T>);
-        while (w > 1 && (w > Lxy || tile(n, w, 1) > AXIS_TILE_BYTES)) w >>= 1;
-        return w;
-    };
-    auto slices = [&](int n, int w, int other) {
-        int b = 8;
-        while (b > 1 && (other % b != 0 || tile(n, w, b) > AXIS_TILE_BYTES)) b >>= 1;
-        return b;
-    };
-    p.rc = false;
-    p.Wz = width(g.Lz);
-    p.Wt = width(g.Lt);
-    p.W = p.Wz;
-    p.Bz = slices(g.Lz, p.Wz, g.Lt);
-    p.Bt = slices(g.Lt, p.Wt, g.Lz);
-    p.ldsz = tile(g.Lz, p.Wz, p.Bz);
-    p.ldst = tile(g.Lt, p.Wt, p.Bt);
-    p.lds = std::max(p.ldsz, p.ldst);
-    return p;
-}
-
-template <class T> void fft_set_max_lds(const geom &g, const zt_plan &p) {
-    auto set = [](const void *f, size_t b) {
-        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
-    };
-    if (p.rc) {
-#define LGF_ZTA(NN)                                                                 \
-    case NN:                                                                        \
-        set(reinterpret_cast<const void *>(&k_fft_zt_rc<T, NN, 0>), p.lds);        \
-        set(reinterpret_cast<const void *>(&k_fft_zt_rc<T, NN, -1>), p.lds);       \
-        set(reinterpret_cast<const void *>(&k_fft_zt_rc<T, NN, 1>), p.lds);        \
-        break;
-        switch (g.Lt) {
-            LGF_NA_CASES(LGF_ZTA)
-        default: break;
-        }
-#undef LGF_ZTA
-    } else {
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 2, -1, 16>), p.ldsz);
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 2, 1, 16>), p.ldsz);
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, 0, 16>), p.ldst);
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, -1, 16>), p.ldst);
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, 1, 16>), p.ldst);
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 2, -1, 32>), p.ldsz);
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 2, 1, 32>), p.ldsz);
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, 0, 32>), p.ldst);
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, -1, 32>), p.ldst);
-        set(reinterpret_cast<const void *>(&k_fft_axis<T, 3, 1, 32>), p.ldst);
-    }
-    if constexpr (std::is_same<T, float>::value) {
-        if (!xy_use_rc<T>(g) && xy_acc_fusable<T>(g)) {
-            const size_t b = xy_acc_lds_bytes<T>(g);
-            set(reinterpret_cast<const void *>(&k_fft_xy_acc<T, 16, true>), b);
-            set(reinterpret_cast<const void *>(&k_fft_xy_acc<T, 16, false>), b);
-            set(reinterpret_cast<const void *>(&k_fft_xy_acc<T, 32, true>), b);
-            set(reinterpret_cast<const void *>(&k_fft_xy_acc<T, 32, false>), b);
-        }
-    }
-    if (!xy_use_rc<T>(g)) {
-        const size_t b = fft_xy_lds_bytes<T>(g);
-        set(reinterpret_cast<const void *>(&k_fft_xy<T, -1, 16>), b);
-        set(reinterpret_cast<const void *>(&k_fft_xy<T, 1, 16>), b);
-        set(reinterpret_cast<const void *>(&k_fft_xy<T, -1, 32>), b);
-        set(reinterpret_cast<const void *>(&k_fft_xy<T, 1, 32>), b);
-    }
-}
-
 template <class T>
 hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const T *ptab,
-                         T p2max_over_V, const zt_plan &pl, const dev_status *status,
+                         T p2max_over_V, const fft_plan &pl, const dev_status *status,
                          hipStream_t st) {
     const long Lxy = (long)g.Lx * g.Ly;
-    const int W = pl.W;
-    dim3 grid((unsigned)((Lxy + W - 1) / W), (unsigned)g.nf);
     auto Dp = static_cast<vec2_t<T> *>(D);
     auto twp = static_cast<const vec2_t<T> *>(tw);
     if (pl.rc) {
+        const int W = pl.W;
+        dim3 grid((unsigned)((Lxy + W - 1) / W), (unsigned)g.nf);
         const unsigned nt = (unsigned)(W * g.Lz);
 #define LGF_ZT(NN)                                                                                \
     case NN:                                                                                      \
@@ -602,42 +702,24 @@ hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const
                                                             status);                              \
         break;
         switch (g.Lt) {
-            LGF_NA_CASES(LGF_ZT)
+            LGF_FFT_SMALL_EXTENTS(LGF_ZT)
         default: return hipErrorInvalidValue;
         }
 #undef LGF_ZT
         return hipGetLastError();
     }
     // z forward (mode <= 0), the t pass (forward, scaled round trip or
-    // inverse), z inverse (mode >= 0); each axis takes the instance for its
-    // extent's register span
-    const unsigned nf = (unsigned)g.nf;
-    const dim3 gz((unsigned)((Lxy + pl.Wz - 1) / pl.Wz), (unsigned)(g.Lt / pl.Bz), nf);
-    const dim3 gt((unsigned)((Lxy + pl.Wt - 1) / pl.Wt), (unsigned)(g.Lz / pl.Bt), nf);
-    const bool zs = fft_reg_span(g.Lz) <= 16, ts = fft_reg_span(g.Lt) <= 16;
-    hipError_t e = hipSuccess;
-    auto chk = [&] {
-        if (e == hipSuccess) e = hipGetLastError();
-    };
-#define LGF_AXIS(AXN, MD, GRID, LDSB, WW, BB, SMALL)                                              \
-    do {                                                                                          \
-        if (SMALL)                                                                                \
-            k_fft_axis<T, AXN, MD, 16><<<GRID, AXIS_BLOCK, LDSB, st>>>(g, Dp, twp, ptab,          \
-                                                                      p2max_over_V, WW, BB,       \
-                                                                      status);                    \
-        else                                                                                      \
-            k_fft_axis<T, AXN, MD, 32><<<GRID, AXIS_BLOCK, LDSB, st>>>(g, Dp, twp, ptab,          \
-                                                                      p2max_over_V, WW, BB,       \
-                                                                      status);                    \
-        chk();                                                                                    \
-    } while (0)
-    if (mode <= 0) LGF_AXIS(2, -1, gz, pl.ldsz, pl.Wz, pl.Bz, zs);
-    if (mode == 0) LGF_AXIS(3, 0, gt, pl.ldst, pl.Wt, pl.Bt, ts);
-    else if (mode < 0) LGF_AXIS(3, -1, gt, pl.ldst, pl.Wt, pl.Bt, ts);
-    else LGF_AXIS(3, 1, gt, pl.ldst, pl.Wt, pl.Bt, ts);
-    if (mode >= 0) LGF_AXIS(2, 1, gz, pl.ldsz, pl.Wz, pl.Bz, zs);
-#undef LGF_AXIS
-    return e;
+    // inverse), z inverse (mode >= 0)
+    const vec2_t<T> *twz = tw_z<T>(g, twp), *twt = tw_t<T>(g, twp);
+    hipError_t e;
+    if (mode <= 0 && (e = launch_axis<T, -1>(g, Dp, twz, ptab, p2max_over_V, pl.z, status, st)))
+        return e;
+    if (mode == 0) e = launch_axis<T, 0>(g, Dp, twt, ptab, p2max_over_V, pl.t, status, st);
+    else if (mode < 0) e = launch_axis<T, -1>(g, Dp, twt, ptab, p2max_over_V, pl.t, status, st);
+    else e = launch_axis<T, 1>(g, Dp, twt, ptab, p2max_over_V, pl.t, status, st);
+    if (e) return e;
+    if (mode >= 0) return launch_axis<T, 1>(g, Dp, twz, ptab, p2max_over_V, pl.z, status, st);
+    return hipSuccess;
 }
 
 }  // namespace lgf

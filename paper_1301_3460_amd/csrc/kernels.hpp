@@ -110,40 +110,62 @@ hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void 
                          void *G, T c, bool exact, void *GX, double *partials, dev_status *status,
                          const fin_params &fp, hipStream_t st);
 
-// mode: -1 forward only, +1 inverse only (x,y pass: direction)
-template <class T>
-hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw,
-                         const dev_status *status, hipStream_t st);
-// (z,t) pass plan: register-column kernel (rc) or LDS-tile kernel, tile width
-// W (consecutive xy-sites per block) and dynamic LDS bytes.
-struct zt_plan {
-    bool rc;     // register-column kernel (both extents up to 32)
-    int W;       // consecutive xy-sites per block
-    size_t lds;  // LDS bytes (register-column kernel; else the larger pass)
-    // one-axis passes: sites and slices of the other axis per block, LDS bytes
-    int Wz = 1, Wt = 1, Bz = 1, Bt = 1;
-    size_t ldsz = 0, ldst = 0;
+// One-axis pass of the 4D transform: a block holds W consecutive elements of
+// the axis's inner range (the sites below the axis: none for x, x for y, the
+// (x,y) plane for z and t) x the whole axis x B consecutive slices (the sites
+// above the axis; for t, the z slices), so every HBM access is a contiguous
+// row.  Element (w, j, b) sits at w + j*sj + b*sb from the block's first
+// element, and in LDS at b*PB + j*PW + w.
+struct axis_plan {
+    int N = 0;           // extent of the axis
+    int W = 1, B = 1;    // inner elements and slices per block
+    int nslice = 1;      // slices in total (the last group may be ragged)
+    int PW = 1, PB = 1;  // LDS strides of an axis position and of a slice
+    long R = 1;          // length of the inner range (the last row may be ragged)
+    long sj = 0, sb = 0; // HBM strides of the axis and of a slice, in elements
+    size_t lds = 0;      // LDS bytes per block
 };
+// How the 4D transform of a context is split into passes.
+struct fft_plan {
+    // (x,y): 0 register-column kernel (both extents up to 32), 1 whole plane in
+    // LDS, 2 an x pass and a y pass
+    int xy = 0;
+    size_t lds_xy = 0;  // LDS bytes of the (x,y) kernel (modes 0 and 1)
+    // (z,t): register-column kernel (both extents up to 32, W consecutive
+    // xy-sites per block), else a z pass and a t pass
+    bool rc = false;
+    int W = 1;
+    size_t lds = 0;
+    axis_plan x, y, z, t;
+};
+template <class T> fft_plan plan_fft(const geom &g, size_t zt_lds_budget);
+// every kernel of the plan fits the LDS of a compute unit and its grid limits
+bool fft_plan_fits(const fft_plan &p);
+template <class T> void fft_set_max_lds(const geom &g, const fft_plan &p);
+// Twiddle tables: one buffer per real type with the axis tables
+// exp(-2 pi i j / L_mu), j < L_mu, of x, y, z and t one after the other.
+// (x,y) transform, dir -1 forward, +1 inverse
+template <class T>
+hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const fft_plan &pl,
+                         const dev_status *status, hipStream_t st);
 // Inverse (x,y) pass fused with G(x) <- g(x) G(x) (FP32 sweeps of an SU(3)
 // mixed solve; L Delta itself is not stored), when xy_acc_fusable: register-
 // column planes with all 4 fields in one block, or wider planes whose 4
 // fields fit in LDS together.
-template <class T> bool xy_acc_fusable(const geom &g);
+template <class T> bool xy_acc_fusable(const geom &g, const fft_plan &pl);
 template <class T>
-hipError_t launch_fft_xy_inv_acc(const geom &g, void *D, const void *tw, const void *Gold,
-                                 void *Gnew, double c, bool exact, const dev_status *status,
-                                 hipStream_t st);
+hipError_t launch_fft_xy_inv_acc(const geom &g, void *D, const void *tw, const fft_plan &pl,
+                                 const void *Gold, void *Gnew, double c, bool exact,
+                                 const dev_status *status, hipStream_t st);
 // G(x) <- g(x) G(x) from the field L Delta as a kernel of its own (FP32 sweeps
 // of an SU(3) mixed solve whose inverse (x,y) pass cannot take it)
 hipError_t launch_gauge_acc(const geom &g, const void *LD, const void *Gold, void *Gnew, double c,
                             bool exact, const dev_status *status, hipStream_t st);
-template <class T> zt_plan plan_zt(const geom &g, size_t lds_budget);
-template <class T> size_t fft_xy_lds_bytes(const geom &g);
-template <class T> void fft_set_max_lds(const geom &g, const zt_plan &p);
-// mode 0: forward, scale by p2max/(V p2), inverse; -1: forward only; +1: inverse only
+// (z,t) transform.  mode 0: forward, scale by p2max/(V p2), inverse; -1:
+// forward only; +1: inverse only
 template <class T>
 hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const T *ptab,
-                         T p2max_over_V, const zt_plan &pl, const dev_status *status,
+                         T p2max_over_V, const fft_plan &pl, const dev_status *status,
                          hipStream_t st);
 
 // natural <-> transform-position order of 4 fields with component strides

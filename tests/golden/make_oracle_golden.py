@@ -26,6 +26,10 @@ WORKLOADS = {
     "32^4": {"L": (32, 32, 32, 32), "eps": [0.6, 0.45, 0.35], "alpha": 0.08, "tol": 1e-15},
     "8^4": {"L": (8, 8, 8, 8), "eps": [0.5], "alpha": 0.08, "tol": 1e-12},
     "48^3x96": {"L": (48, 48, 48, 96), "eps": [0.45], "alpha": 0.08, "tol": 1e-15},
+    # extents 36 and 72 (two-pass 6x6 and 8x9 transforms) and odd extents
+    # (27 = 3^3, p2max below 16)
+    "36^3x72": {"L": (36, 36, 36, 72), "eps": [0.45], "alpha": 0.08, "tol": 1e-15},
+    "27^4": {"L": (27, 27, 27, 27), "eps": [0.45], "alpha": 0.08, "tol": 1e-15},
     # the same 32^4 input, solved with the exactly exponentiated step
     "32^4-exp": {"L": (32, 32, 32, 32), "eps": [0.45], "alpha": 0.08, "tol": 1e-15,
                  "seeds": "32^4", "exact_exp": True},

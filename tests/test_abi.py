@@ -42,8 +42,8 @@ def _create(L, prec=0):
     return rc, lib.lgf_last_error(None).decode(), h
 
 
-@pytest.mark.parametrize("L", [(5, 4, 4, 4), (4, 4, 4, 0), (4, 4, 4, 9), (4, 4, 4, 256),
-                               (1, 4, 4, 4), (4, -4, 4, 4)])
+@pytest.mark.parametrize("L", [(5, 4, 4, 4), (4, 4, 4, 0), (4, 4, 4, 7), (4, 4, 4, 512),
+                               (4, 4, 4, 384), (1, 4, 4, 4), (4, -4, 4, 4), (10, 4, 4, 4)])
 def test_create_rejects_unsupported_extents_before_touching_the_device(L):
     rc, msg, h = _create(L)
     assert rc == lgf.LGF_ERR_ARG
@@ -89,3 +89,14 @@ def test_measure_noalloc_rejects_arguments_before_touching_the_device():
     assert lib.lgf_measure_noalloc(ctypes.byref(bad), out, out, None) == lgf.LGF_ERR_ARG
     ok = (ctypes.c_int * 4)(4, 4, 4, 4)
     assert lib.lgf_measure_noalloc(ctypes.byref(ok), None, out, None) == lgf.LGF_ERR_ARG
+
+
+@pytest.mark.parametrize("L", [(9, 18, 27, 36), (72, 144, 2, 2), (192, 4, 4, 4), (256, 2, 2, 2),
+                               (243, 81, 2, 2), (54, 108, 162, 2), (216, 3, 3, 3)])
+def test_create_accepts_every_2a3b_extent_up_to_256(L):
+    """Every 2^a 3^b extent from 2 to 256 passes the argument checks (on a host
+    without a GPU the call then stops at the device lookup)."""
+    rc, msg, h = _create(L)
+    assert rc != lgf.LGF_ERR_ARG, msg
+    if h.value:
+        lgf.load().lgf_destroy(h)

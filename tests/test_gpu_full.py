@@ -187,3 +187,36 @@ def test_solve_48x3x96(lgf_gpu, config48, precision):
     assert mu <= 1e-13 and md <= 1e-13
     if precision == "fp64":
         assert abs(r.iterations - ref["iterations"]) <= 1
+
+
+# Extents beyond the powers of two and 48/96: 36 = 6x6 and 72 = 8x9 two-pass
+# transforms (36^3 x 72, 3.4M sites), and odd extents 27 = 3^3 with p2max
+# below 16 (27^4).  Reference values from tests/golden/make_oracle_golden.py.
+OTHER = {"27^4": ((27, 27, 27, 27), "oracle_274.json"),
+         "36^3x72": ((36, 36, 36, 72), "oracle_363x72.json")}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", sorted(OTHER))
+def test_solve_other_extents(lgf_gpu, name, precision):
+    L, fname = OTHER[name]
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", fname)) as f:
+        ref = json.load(f)["runs"][0]
+    print(f"solve {name} {precision}", flush=True)
+    U = inputs.make_config(L, ref["eps"], inputs.CONFIG_SEEDS[(name, ref["eps"])])[0]
+    assert oracle.plaquette(U) == pytest.approx(ref["plaquette_in"], abs=1e-13)
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, 0.08, 1e-15, precision=precision, max_iter=2000)
+    assert r.status == 0
+    out = Ug.cpu().numpy()
+    del Ug
+    assert oracle.theta(out) < 1e-15
+    assert abs(r.F - ref["F"]) <= 1e-12
+    assert abs(oracle.F(out) - ref["F"]) <= 1e-12
+    assert abs(oracle.plaquette(out) - ref["plaquette_in"]) <= 1e-12
+    mu, md = oracle.unitarity(out)
+    assert mu <= 1e-13 and md <= 1e-13
+    if precision == "fp64":
+        assert abs(r.iterations - ref["iterations"]) <= 1
+    else:
+        assert 0 < r.fp32_iterations < r.iterations <= ref["iterations"] + 2

@@ -41,6 +41,11 @@ def _check_solution(Uout, Uin, tol, F):
     ((32, 8, 4, 4), 0.5, 80, 1e-14),
     ((48, 4, 4, 6), 0.5, 79, 1e-14),
     ((32, 48, 2, 2), 0.5, 82, 1e-14),
+    # odd extents (p2max below 16) and two-pass / one-axis transform extents
+    ((9, 9, 9, 9), 0.5, 83, 1e-14),
+    ((27, 4, 6, 9), 0.5, 84, 1e-14),
+    ((36, 4, 6, 72), 0.5, 85, 1e-14),
+    ((256, 48, 2, 2), 0.5, 86, 1e-14),
 ])
 def test_solve_matches_oracle(lgf_gpu, L, eps, seed, tol, precision):
     U, _ = inputs.make_config(L, eps, seed)
@@ -124,7 +129,8 @@ def test_bad_arguments_raise(lgf_gpu):
 # in the inverse (x,y) pass (8 and 32 wide), the 4-field LDS kernel for wider
 # planes with register spans up to 16 (48 wide) and 32 (Ly = 48 beside Lx = 32)
 @pytest.mark.parametrize("L,seed", [((8, 8, 8, 8), 35), ((32, 8, 4, 4), 36), ((48, 4, 4, 6), 37),
-                                    ((32, 48, 2, 2), 38)])
+                                    ((32, 48, 2, 2), 38), ((27, 9, 4, 6), 39),
+                                    ((256, 48, 2, 2), 40)])
 def test_mixed_iterate_applies_accumulated_transformation(lgf_gpu, L, seed):
     """FP32-phase lockstep: a mixed-precision context runs FP32 sweeps and
     applies the accumulated transformation to the FP64 input, so the result is

@@ -3,7 +3,9 @@
 Every check compares the library, called through its C ABI, element by element
 with the oracle on the same seeded inputs.  Shapes span several tiles, ragged
 tails (xy-planes not a multiple of the (z,t) tile width, volumes not a
-multiple of the site block) and the two-pass FFT extents (48, 64, 96, 128).
+multiple of the site block), every extent 2^a 3^b up to 256 (odd ones
+included) and each transform scheme: register columns, whole planes in LDS,
+one-axis passes, two-pass extents.
 Bars: 1e-13 absolute on O(1) quantities (FP64 rounding of a few hundred
 operations; the oracle and the kernels order their sums differently).
 """
@@ -23,6 +25,15 @@ SHAPES = [
     (32, 48, 2, 2), (2, 2, 32, 64), (2, 4, 96, 24),
     # 32-wide x rows with even and odd Ly
     (32, 6, 4, 2), (32, 24, 2, 2), (32, 2, 3, 4), (32, 3, 2, 4),
+    # the other extents 2^a 3^b up to 256 on each axis: register columns (9, 18,
+    # 27; odd extents, p2max below 16), whole-plane and one-axis transforms
+    # (36 ... 256, two passes N1 x N2 with spans up to 16 and up to 32)
+    (9, 4, 3, 2), (4, 9, 2, 6), (18, 18, 3, 4), (27, 2, 9, 4), (2, 3, 27, 27), (3, 2, 9, 18),
+    (36, 4, 2, 4), (4, 54, 2, 2), (2, 2, 72, 3), (2, 3, 2, 81), (108, 2, 3, 2),
+    (144, 4, 2, 2), (4, 2, 162, 2), (2, 2, 2, 192), (216, 2, 2, 3), (2, 243, 2, 2),
+    (256, 2, 2, 2), (2, 2, 4, 256), (27, 27, 3, 2),
+    # (x,y) planes beyond one LDS tile: a separate x pass and y pass
+    (256, 48, 2, 2), (243, 81, 2, 2),
 ]
 
 
@@ -96,7 +107,9 @@ def test_link_storage_round_trip(lgf_gpu):
 
 @pytest.mark.parametrize("L", [(4, 4, 4, 4), (8, 8, 8, 8), (4, 6, 8, 12), (2, 3, 4, 6),
                                (48, 4, 4, 6), (4, 6, 4, 96), (12, 12, 12, 12),
-                               (16, 16, 16, 16), (32, 8, 8, 6)])
+                               (16, 16, 16, 16), (32, 8, 8, 6),
+                               (9, 9, 9, 9), (18, 27, 4, 6), (36, 4, 6, 72), (256, 4, 4, 4),
+                               (4, 4, 144, 4), (6, 6, 6, 192), (256, 48, 2, 2)])
 def test_lockstep_sweeps(lgf_gpu, L):
     """Feed the GPU state to the oracle, take one sweep on each side, compare
     the links; repeat.  Also checks F and theta reported for the new links."""

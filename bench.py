@@ -34,6 +34,7 @@ EPS_ALL = (0.6, 0.45, 0.35)
 EPS_MAIN = 0.45
 REPS = 5  # repeats per timed iterate() length (medians)
 BYTES_UPDATE_18 = 4 * 144 * 2 + 128  # update with 18-real links: R+W 4 x 144 B, R+W 64 B
+BYTES_UPDATE_8 = 4 * 64 * 2 + 128  # update with 8-real links: R+W 4 x 64 B, R+W 64 B
 BYTES_UPDATE_SU2 = 4 * 32 * 2 + 32 * 2  # SU(2) update: R+W 4 links x 32 B, R+W 2 fields
 SD_TOL = 1e-10  # plain steepest descent needs thousands of sweeps at 32^4
 # algorithmic bytes per site of each sweep kernel: FP64, and the FP32 sweeps
@@ -353,6 +354,20 @@ def main() -> int:
         "solve_ms": round(1e3 * t, 3), "iterations": res.iterations,
         "F": res.F, "dF_vs_oracle": abs(res.F - golden[EPS_MAIN]["F"]) if golden else None}
     log(f"18-real links: {variants['link18/fp64']}")
+    # the minimal 8-real working links (one third less link traffic, decoding
+    # arithmetic instead)
+    ctx64.set_link_format(8)
+    ss8 = steady_sweeps(ctx64, U0, work, args.steps)
+    upd8 = ctx64.profile(U0, ALPHA, 20)["update"]
+    t, res = solve_timing(ctx64, U0, work, args.solves)
+    ctx64.set_link_format(12)
+    variants["link8/fp64"] = {
+        "sweeps_per_s": round(1.0 / ss8["s_per_sweep"], 1), "update_ms": round(upd8, 5),
+        "update_GBps": round(BYTES_UPDATE_8 * V / (upd8 * 1e-3) / 1e9, 1),
+        "update_bytes_per_site": BYTES_UPDATE_8,
+        "solve_ms": round(1e3 * t, 3), "iterations": res.iterations,
+        "F": res.F, "dF_vs_oracle": abs(res.F - golden[EPS_MAIN]["F"]) if golden else None}
+    log(f"8-real links: {variants['link8/fp64']}")
     # SU(2) on the same lattice (N_c = 2; links stored as row 0)
     U2 = inputs.make_config_su2(L, EPS_MAIN, inputs.CONFIG_SEEDS[("su2 32^4", EPS_MAIN)])[0]
     U2 = torch.from_numpy(U2).to("cuda")

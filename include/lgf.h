@@ -140,11 +140,18 @@ int lgf_set_exponential(lgf_ctx *ctx, int exact);
  * LGF_ERR_ARG for other values. */
 int lgf_set_field_precision(lgf_ctx *ctx, int bits);
 
-/* Storage of the working links during lgf_fix / lgf_iterate: nreal = 12
- * (default; the paper's "12 real number representation": rows 0 and 1, row 2
- * rebuilt as conj(row0 x row1) on every load) or 18 (all three rows stored, no
- * rebuild, 50% more link traffic).  The caller's links are always full 3x3
- * complex128; the other entry points always use 12.  Changing the format
+/* Storage of the working links during lgf_fix / lgf_iterate (the paper's
+ * GPU paragraph picks its 12-real form for speed; the alternatives trade
+ * bytes against arithmetic): nreal = 12 (default; the paper's "12 real number
+ * representation": rows 0 and 1, row 2 rebuilt as conj(row0 x row1) on every
+ * load), 18 (all three rows stored, no rebuild, 50% more link traffic) or 8
+ * (the minimal form: a link is brought to a frame whose stored entries leave
+ * every reconstruction step well conditioned -- no singular set -- and
+ * rebuilt from 6 matrix entries, two phases held as tan(phi/4) and 3
+ * permutation bits in the lowest mantissa bits of one stored entry; one
+ * third less link traffic, more arithmetic, about 1e-15 per store in FP64).
+ * The caller's links are always full 3x3 complex128 (rows 0,1 read for 12
+ * and 8); the other entry points always use 12.  Changing the format
  * reallocates the context's link buffers (synchronises the stream).
  * LGF_ERR_ARG for another nreal; LGF_ERR_OOM if the new buffers do not fit (the
  * context then holds 12-real buffers again, or none, which later calls

@@ -199,8 +199,8 @@ class Context:
             self._err(rc)
 
     def set_link_format(self, nreal: int):
-        """12 (default, rows 0,1 stored) or 18 (all rows stored) reals per
-        working link in fix/iterate."""
+        """12 (default, rows 0,1 stored), 18 (all rows stored) or 8 (the minimal
+        SU(3) form) reals per working link in fix/iterate."""
         rc = self._lib.lgf_set_link_format(self._h, int(nreal))
         if rc:
             self._err(rc)
@@ -372,7 +372,7 @@ def fix(U, alpha=0.08, theta_tol=1e-15, precision="fp64", max_iter=10000, theta_
     """Gauge-fix U in place; returns a Result (iterations, F, theta, status).
     accelerate=False runs plain (unaccelerated) steepest descent; exact_exp=True
     exponentiates the step exactly; link_format=18 stores all three rows of
-    the working links."""
+    the working links, link_format=8 the minimal 8-real form."""
     c = _ctx(U, precision)
     if precision == "mixed":
         c.set_theta_switch(theta_switch)

@@ -332,20 +332,20 @@ int status_to_code(int code) {
 // the caller's links themselves).
 geom g12(const lgf_ctx *c) {
     geom g = c->g;
-    g.nr = 2;
+    g.lf = 12;
     g.ff32 = 0;  // these entry points read the field back in FP64
     return g;
 }
 
 // (Re)allocate the working link buffers for the context's link format: each
-// holds 4 links x (3*nr for SU(3), 2 for SU(2)) complex entries per site
+// holds 4 links x (lf/2 for SU(3), 2 for SU(2)) complex entries per site
 // (FP64); the FP32 pair aliases the second buffer.
 bool alloc_links(lgf_ctx *c) {
     for (auto &p : c->L64) {
         if (p) (void)hipFree(p);
         p = nullptr;
     }
-    const size_t n = (size_t)4 * (c->g.nc == 2 ? 2 : 3 * c->g.nr) * c->g.S;
+    const size_t n = (size_t)4 * (c->g.nc == 2 ? 2 : c->g.lf / 2) * c->g.S;
     for (auto &p : c->L64)
         if (hipMalloc((void **)&p, n * sizeof(double2)) != hipSuccess) return false;
     c->L32[0] = reinterpret_cast<float2 *>(c->L64[1]);
@@ -607,15 +607,15 @@ int lgf_set_acceleration(lgf_ctx *c, int on) {
 
 int lgf_set_link_format(lgf_ctx *c, int nreal) {
     if (!c) return LGF_ERR_ARG;
-    if (nreal != 12 && nreal != 18) return fail(c, LGF_ERR_ARG, "link format must be 12 or 18");
+    if (nreal != 12 && nreal != 18 && nreal != 8)
+        return fail(c, LGF_ERR_ARG, "link format must be 8, 12 or 18");
     if (c->g.nc != 3) return fail(c, LGF_ERR_ARG, "link formats apply to SU(3) contexts");
-    const int nr = nreal / 6;
-    if (nr == c->g.nr) return LGF_OK;
+    if (nreal == c->g.lf) return LGF_OK;
     if (hipSetDevice(c->device) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
         return fail(c, LGF_ERR_DEVICE, "device unavailable");
-    c->g.nr = nr;
+    c->g.lf = nreal;
     if (!alloc_links(c)) {
-        c->g.nr = 2;
+        c->g.lf = 12;
         (void)alloc_links(c);  // on failure the buffers stay null; check_ctx reports it
         return fail(c, LGF_ERR_OOM, "out of device memory (links)");
     }

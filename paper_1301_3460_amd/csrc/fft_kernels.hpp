@@ -45,18 +45,6 @@ template <class T> __host__ __device__ inline const vec2_t<T> *tw_t(const geom &
     return tw + g.Lx + g.Ly + g.Lz;
 }
 
-// 1/x from the hardware estimate refined by Newton steps (to about 1 ulp).
-__device__ __forceinline__ double recip(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
-    r = fma(r, fma(-x, r, 1.0), r);
-    return r;
-}
-__device__ __forceinline__ float recip(float x) {
-    float r = __builtin_amdgcn_rcpf(x);
-    return fmaf(r, fmaf(-x, r, 1.0f), r);
-}
-
 // Momentum-space factor p2max/(V p2) of one (z,t) column: `base` is the
 // column's p2 without the z term (negative for a padding column).
 template <class T>

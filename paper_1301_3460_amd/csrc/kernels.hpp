@@ -53,8 +53,9 @@ struct geom {
     // site-kernel tiling (see block_site): 0 consecutive sites; 1 64 xy-sites
     // x 4 t (needs Lx*Ly % 64 == 0, Lt % 4 == 0), in groups of sgroup segments
     int tblock = 0, sgroup = 1;
-    // stored rows per working link: 2 (12-real, row 2 rebuilt) or 3 (18-real)
-    int nr = 2;
+    // working link format, reals per link: 12 (rows 0,1; row 2 rebuilt), 18
+    // (all three rows) or 8 (the minimal form of su3.hpp)
+    int lf = 12;
     // gauge group SU(nc), nc = 3 or 2, and the number of complex Fourier
     // fields carrying Delta (4 for SU(3), 2 for SU(2))
     int nc = 3, nf = 4;
@@ -79,7 +80,7 @@ inline geom make_geom(const int L[4], int nc) {
     g.S = g.V + SOA_PAD;
     g.nc = nc;
     g.nf = nc == 3 ? 4 : 2;
-    g.nr = 2;
+    g.lf = 12;
     g.ff32 = 0;
     g.tblock = ((long)L[0] * L[1] % 64 == 0 && L[3] % 4 == 0) ? 1 : 0;
     const long nseg = (long)L[0] * L[1] / 64;

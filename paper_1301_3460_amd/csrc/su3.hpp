@@ -99,6 +99,18 @@ LGF_HD float rsqrt_nr(float x) {
     return fmaf(0.5f * y, e, y);
 }
 
+// 1/x from the hardware estimate refined by Newton steps (to about 1 ulp).
+LGF_HD double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+LGF_HD float recip(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 // Gram-Schmidt on rows 0,1 (in place), then rebuild row 2.
 template <class T> LGF_HD void reunitarise(mat3<T> &m) {
     T n0 = norm2(m.e[0][0]) + norm2(m.e[0][1]) + norm2(m.e[0][2]);
@@ -144,31 +156,186 @@ LGF_HD mat3<T> mul_abcd(const mat3<T> &A, const mat3<T> &B, const mat3<T> &C) {
 }
 
 // ------------------------------------------------------------------------
+// Minimal 8-real link storage
+//
+// An SU(3) matrix has 8 real degrees of freedom, but no single set of 8
+// matrix coordinates covers the group without a singular set (the usual
+// form, U01, U02, U10 and the phases of U00 and U20, divides by 1 - |U00|^2
+// and loses the lower block entirely on diagonal links).  Here every link is
+// first brought to a well-conditioned frame V = R U P: P permutes the columns
+// so that row 0 reads (smallest, middle, largest modulus) and R swaps rows 1
+// and 2 when that makes |V20| >= |V10|.  Then |V00|^2 <= 1/3, |V02|^2 >= 1/3
+// and |V20|^2 >= 1/3, and the stored reals are
+//     V00 (2), V01 (2), V10 (2), tan(phi/4) of the phases of V02 and V20 (2),
+// with the permutation (3 columns x parity, 2 bits) and the row swap (1 bit)
+// in the two lowest mantissa bits of Re V01 and Im V01.  Decoding derives
+// |V02| and |V20| from the unit norms of row 0 and column 0 (no cancellation:
+// both are at least 1/3), the remaining 2x2 block from the cofactor identity
+// of a unitary matrix of determinant d = det R det P = +-1,
+//     conj(V_ij) = C_ij / d,
+// which divides only by 1 - |V00|^2 >= 2/3, and undoes R and P.  The phase
+// codes are rational in tan(phi/4) (no trigonometric functions), and every
+// step is well conditioned, so a round trip changes a link by about 1e-15 in
+// FP64.  The tag bits perturb Re V01 and Im V01 by at most 3 ulp.
+// ------------------------------------------------------------------------
+
+LGF_HD double with_tag(double v, int b) {
+    return __longlong_as_double((__double_as_longlong(v) & ~3LL) | (long long)b);
+}
+LGF_HD float with_tag(float v, int b) { return __int_as_float((__float_as_int(v) & ~3) | b); }
+LGF_HD int tag_of(double v) { return (int)(__double_as_longlong(v) & 3); }
+LGF_HD int tag_of(float v) { return __float_as_int(v) & 3; }
+LGF_HD double untag(double v) { return __longlong_as_double(__double_as_longlong(v) & ~3LL); }
+LGF_HD float untag(float v) { return __int_as_float(__float_as_int(v) & ~3); }
+
+// tan(phi/4) of z = |z| e^{i phi}, phi in [-pi, pi] (0 for z = 0): the phase
+// as one real in [-1, 1].  w = e^{i phi/2} with Re w >= 0 comes from the
+// half-angle formulas in whichever form has no cancellation.
+template <class T> LGF_HD T quarter_tan(cpx<T> z) {
+    const T r2 = norm2(z);
+    if (!(r2 > T(0))) return T(0);
+    const T ir = rsqrt_nr(r2);
+    const T c = z.re * ir, sn = z.im * ir;
+    const T h = T(1) / T(2) * (T(1) + fabs(c));
+    const T hs = h * rsqrt_nr(h);              // sqrt((1 + |c|)/2) >= 1/sqrt(2)
+    const T q = T(0.5) * sn * recip(hs);       // the other half-angle component
+    const T wr = c >= T(0) ? hs : fabs(q);
+    const T wi = c >= T(0) ? q : copysign(hs, sn);
+    return wi * recip(T(1) + wr);
+}
+
+// e^{i phi} from t = tan(phi/4)
+template <class T> LGF_HD cpx<T> phase_of_quarter_tan(T t) {
+    const T t2 = t * t, d = recip(T(1) + t2);
+    const T hr = (T(1) - t2) * d, hi = T(2) * t * d;  // e^{i phi/2}
+    return mk<T>(fma(hr, hr, -hi * hi), T(2) * hr * hi);
+}
+
+// sqrt(x) for x >= 0 (0 for x <= 0)
+template <class T> LGF_HD T sqrt_nonneg(T x) { return x > T(0) ? x * rsqrt_nr(x) : T(0); }
+
+template <class T> LGF_HD cpx<T> sel3(int j, cpx<T> a, cpx<T> b, cpx<T> c) {
+    return j == 0 ? a : (j == 1 ? b : c);
+}
+
+template <class T> LGF_HD void link8_encode(const mat3<T> &m, cpx<T> (&u)[4]) {
+    const T n0 = norm2(m.e[0][0]), n1 = norm2(m.e[0][1]), n2 = norm2(m.e[0][2]);
+    // c0: column of the smallest row-0 entry; c2: the larger of the other two
+    const int c0 = (n0 <= n1 && n0 <= n2) ? 0 : (n1 <= n2 ? 1 : 2);
+    const int j = c0 == 0 ? 1 : 0, k = c0 == 2 ? 1 : 2;
+    const T nj = c0 == 0 ? n1 : n0, nk = c0 == 2 ? n1 : n2;
+    const int c2 = nk > nj ? k : j, c1 = 3 - c0 - c2;
+    const bool odd = c2 == (c0 == 2 ? 0 : c0 + 1);  // (c0, c1, c2) not a cyclic shift
+    const cpx<T> x10 = sel3(c0, m.e[1][0], m.e[1][1], m.e[1][2]);
+    const cpx<T> x20 = sel3(c0, m.e[2][0], m.e[2][1], m.e[2][2]);
+    const bool swap = norm2(x10) > norm2(x20);
+    const cpx<T> v01 = sel3(c1, m.e[0][0], m.e[0][1], m.e[0][2]);
+    u[0] = sel3(c0, m.e[0][0], m.e[0][1], m.e[0][2]);
+    u[1] = mk<T>(with_tag(v01.re, c0), with_tag(v01.im, (odd ? 1 : 0) | (swap ? 2 : 0)));
+    u[2] = swap ? x20 : x10;
+    u[3] = mk<T>(quarter_tan(sel3(c2, m.e[0][0], m.e[0][1], m.e[0][2])),
+                 quarter_tan(swap ? x10 : x20));
+}
+
+template <class T> LGF_HD mat3<T> link8_decode(const cpx<T> (&u)[4]) {
+    const int t0 = tag_of(u[1].re), bits = tag_of(u[1].im);
+    const int c0 = t0 > 2 ? 2 : t0;
+    const bool odd = (bits & 1) != 0, swap = (bits & 2) != 0;
+    const int c2 = odd ? (c0 == 2 ? 0 : c0 + 1) : (c0 == 0 ? 2 : c0 - 1);
+    const int c1 = 3 - c0 - c2;
+    const cpx<T> a0 = u[0], a1 = mk<T>(untag(u[1].re), untag(u[1].im)), b0 = u[2];
+    const T n0 = norm2(a0);
+    const cpx<T> a2 = sqrt_nonneg(T(1) - n0 - norm2(a1)) * phase_of_quarter_tan(u[3].re);
+    const cpx<T> cc = sqrt_nonneg(T(1) - n0 - norm2(b0)) * phase_of_quarter_tan(u[3].im);
+    const T inv = recip(T(1) - n0);
+    const T d = odd != swap ? T(-1) : T(1);  // det of the frame V
+    // V11 = -(conj(a0) a1 b0 + d conj(a2) conj(cc)) / (1 - |a0|^2)
+    // V12 = (d conj(a1) conj(cc) - conj(a0) a2 b0) / (1 - |a0|^2)
+    // V21 = d (conj(a2) conj(b0) - conj(a0) conj(V12))
+    // V22 = d (conj(a0) conj(V11) - conj(a1) conj(b0))
+    const cpx<T> ab = cmul(a1, b0), a2b = cmul(a2, b0);
+    const cpx<T> ac = conjg(cmul(a2, cc)), a1c = conjg(cmul(a1, cc));
+    const cpx<T> v11 = (-inv) * (cmulc(ab, a0) + d * ac);
+    const cpx<T> v12 = inv * (d * a1c - cmulc(a2b, a0));
+    const cpx<T> v21 = d * (conjg(cmul(a2, b0)) - conjg(cmul(a0, v12)));
+    const cpx<T> v22 = d * (conjg(cmul(a0, v11)) - conjg(cmul(a1, b0)));
+    // undo the row swap, then the column permutation (V column k is U column ck)
+    const cpx<T> r1[3] = {swap ? cc : b0, swap ? v21 : v11, swap ? v22 : v12};
+    const cpx<T> r2[3] = {swap ? b0 : cc, swap ? v11 : v21, swap ? v12 : v22};
+    const cpx<T> r0[3] = {a0, a1, a2};
+    mat3<T> m;
+#pragma unroll
+    for (int col = 0; col < 3; ++col) {
+        const int src = col == c0 ? 0 : (col == c1 ? 1 : 2);
+        m.e[0][col] = sel3(src, r0[0], r0[1], r0[2]);
+        m.e[1][col] = sel3(src, r1[0], r1[1], r1[2]);
+        m.e[2][col] = sel3(src, r2[0], r2[1], r2[2]);
+    }
+    return m;
+}
+
+// ------------------------------------------------------------------------
 // Storage layouts
-//   links SoA:     L[(mu*3*NR + k)*S + s], k = 3*row + col for the NR stored
-//                  rows: NR = 2 is the 12-real form (rows 0,1; row 2 rebuilt
-//                  as conj(row0 x row1)), NR = 3 the 18-real form (no rebuild)
+//   links SoA:     L[(mu*LF/2 + k)*S + s], LF/2 complex slots per link for
+//                  the link format LF (reals per link):
+//                  LF = 12: rows 0,1 (k = 3*row + col); row 2 rebuilt as
+//                           conj(row0 x row1) -- the paper's 12-real form
+//                  LF = 18: all three rows (no rebuild)
+//                  LF = 8:  the minimal form above (4 slots)
 //   Fourier field: D[f*S + s], f = 0..3 holding the independent entries of
 //                  an anti-hermitian traceless matrix:
 //                  f0 = M01, f1 = M02, f2 = M12,
 //                  f3 = (Im M00) + i (Im M11)
 // ------------------------------------------------------------------------
 
-template <class T, int NR = 2>
-LGF_HD mat3<T> load_link(const vec2_t<T> *__restrict__ L, long S, int mu, long s) {
-    mat3<T> m;
-    const vec2_t<T> *p = L + (long)mu * 3 * NR * S + s;
+// rows formed by products when a link is computed for storage in format LF
+// (the rest rebuilt): all three for the 18-real form
+template <int LF> constexpr int product_rows() { return LF == 18 ? 3 : 2; }
+
+template <class T, int LF> LGF_HD mat3<T> link_from_slots(const cpx<T> (&u)[LF / 2]) {
+    if constexpr (LF == 8) {
+        return link8_decode<T>(u);
+    } else {
+        mat3<T> m;
 #pragma unroll
-    for (int k = 0; k < 3 * NR; ++k) m.e[k / 3][k % 3] = ld<T>(p + (long)k * S);
-    if constexpr (NR == 2) rebuild_row2(m);
-    return m;
+        for (int k = 0; k < LF / 2; ++k) m.e[k / 3][k % 3] = u[k];
+        if constexpr (LF == 12) rebuild_row2(m);
+        return m;
+    }
 }
 
-template <class T, int NR = 2>
-LGF_HD void store_link(vec2_t<T> *__restrict__ L, long S, int mu, long s, const mat3<T> &m) {
-    vec2_t<T> *p = L + (long)mu * 3 * NR * S + s;
+template <class T, int LF> LGF_HD void link_to_slots(const mat3<T> &m, cpx<T> (&u)[LF / 2]) {
+    if constexpr (LF == 8) {
+        link8_encode<T>(m, u);
+    } else {
 #pragma unroll
-    for (int k = 0; k < 3 * NR; ++k) st_stream<T>(p + (long)k * S, m.e[k / 3][k % 3]);
+        for (int k = 0; k < LF / 2; ++k) u[k] = m.e[k / 3][k % 3];
+    }
+}
+
+// the link as it reads back after storage in format LF
+template <class T, int LF> LGF_HD mat3<T> as_stored(const mat3<T> &m) {
+    cpx<T> u[LF / 2];
+    link_to_slots<T, LF>(m, u);
+    return link_from_slots<T, LF>(u);
+}
+
+template <class T, int LF = 12>
+LGF_HD mat3<T> load_link(const vec2_t<T> *__restrict__ L, long S, int mu, long s) {
+    cpx<T> u[LF / 2];
+    const vec2_t<T> *p = L + (long)mu * (LF / 2) * S + s;
+#pragma unroll
+    for (int k = 0; k < LF / 2; ++k) u[k] = ld<T>(p + (long)k * S);
+    return link_from_slots<T, LF>(u);
+}
+
+template <class T, int LF = 12>
+LGF_HD void store_link(vec2_t<T> *__restrict__ L, long S, int mu, long s, const mat3<T> &m) {
+    cpx<T> u[LF / 2];
+    link_to_slots<T, LF>(m, u);
+    vec2_t<T> *p = L + (long)mu * (LF / 2) * S + s;
+#pragma unroll
+    for (int k = 0; k < LF / 2; ++k) st_stream<T>(p + (long)k * S, u[k]);
 }
 
 // g = reunit(1 + c * M) for the anti-hermitian traceless M whose 4 Fourier-

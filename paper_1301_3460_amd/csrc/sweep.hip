@@ -25,26 +25,35 @@ namespace lgf {
 // layout conversion
 // ---------------------------------------------------------------------------
 
-// complex128 [4][V][3][3] -> SoA of type T (the first NR rows)
-template <class T, int NR>
+// A caller link (complex128 AoS, rows 0,1; all three rows for the 18-real
+// format) as an SU(3) matrix of type T.
+template <class T, int LF> __device__ __forceinline__ mat3<T> aos_link(const double2 *__restrict__ u) {
+    constexpr int NIN = LF == 18 ? 9 : 6;
+    mat3<T> m;
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) {
+        const double2 v = u[k];
+        m.e[k / 3][k % 3] = mk<T>((T)v.x, (T)v.y);
+    }
+    if constexpr (LF != 18) rebuild_row2(m);
+    return m;
+}
+
+// complex128 [4][V][3][3] -> SoA of type T in link format LF
+template <class T, int LF>
 __global__ void __launch_bounds__(256) k_pack_links(const double2 *__restrict__ U,
                                                     vec2_t<T> *__restrict__ L, long V, long S) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 4 * V) return;
     const int mu = (int)(i / V);
     const long s = i - (long)mu * V;
-    const double2 *u = U + i * 9;
+    cpx<T> sl[LF / 2];
+    link_to_slots<T, LF>(aos_link<T, LF>(U + i * 9), sl);
 #pragma unroll
-    for (int k = 0; k < 3 * NR; ++k) {
-        double2 v = u[k];
-        vec2_t<T> w;
-        w.x = (T)v.x;
-        w.y = (T)v.y;
-        L[((long)mu * 3 * NR + k) * S + s] = w;
-    }
+    for (int k = 0; k < LF / 2; ++k) st<T>(L + ((long)mu * (LF / 2) + k) * S + s, sl[k]);
 }
 
-template <int NR>
+template <int LF>
 __global__ void __launch_bounds__(256) k_unpack_links(const double2 *__restrict__ L,
                                                       double2 *__restrict__ U, long V, long S) {
     // The block's 256 links are assembled in LDS and written out as one
@@ -56,7 +65,7 @@ __global__ void __launch_bounds__(256) k_unpack_links(const double2 *__restrict_
     if (i < 4 * V) {
         const int mu = (int)(i / V);
         const long s = i - (long)mu * V;
-        const mat3<double> m = load_link<double, NR>(L, S, mu, s);
+        const mat3<double> m = load_link<double, LF>(L, S, mu, s);
 #pragma unroll
         for (int k = 0; k < 9; ++k)
             buf[threadIdx.x * 9 + k] = make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
@@ -206,7 +215,7 @@ __device__ __forceinline__ T divergence_at(const geom &g, long s, LinkFn link, c
     return delta_pack(X, f[0], f[1], f[2], f[3]);
 }
 
-template <class T, class TF, int NR>
+template <class T, class TF, int LF>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_div_reduce(geom g, const vec2_t<T> *__restrict__ L, vec2_t<TF> *__restrict__ D,
                  double *__restrict__ partials, const dev_status *__restrict__ status) {
@@ -217,7 +226,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         cpx<T> f[4];
         T tr;
         ts = (double)divergence_at<T>(
-            g, s, [&](int mu, long x) { return load_link<T, NR>(L, g.S, mu, x); }, f, tr);
+            g, s, [&](int mu, long x) { return load_link<T, LF>(L, g.S, mu, x); }, f, tr);
         fs = (double)tr;
 #pragma unroll
         for (int k = 0; k < 4; ++k) st<TF>(D + k * g.S + s, cvt<TF>(f[k]));
@@ -258,7 +267,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 // accumulated G of the FP32 sweeps (k_gauge_acc), whose links G U0 G^dagger
 // come from the constant input copy U0 in Lin.  STORE: write the new links to
 // Lout (the FP32 sweeps keep U0 and G instead).
-template <class T, class TF, bool GPRE, int NR, bool STORE>
+template <class T, class TF, bool GPRE, int LF, bool STORE>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_update(geom g, const vec2_t<T> *__restrict__ Lin, vec2_t<T> *__restrict__ Lout,
              const vec2_t<TF> *__restrict__ LD, const vec2_t<T> *__restrict__ GX,
@@ -272,12 +281,12 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         // Eight half-steps h = 2 mu + b: b = 0 transforms the link U_mu(x)
         // with g(x+mu), b = 1 the link U_mu(x-mu) with g(x-mu).  Each needs
         // the 4 field entries of g's site (6 entries of g itself when GPRE)
-        // and 3*NR link entries; the loads of half-step h+1 are issued before
+        // and the LF/2 stored slots of the link; the loads of half-step h+1 are issued before
         // half-step h is computed (software pipelining), so every wave keeps
         // the next memory round trip in flight.
         constexpr int NG = GPRE ? 6 : 4;
         struct half {
-            cpx<T> f[NG], u[3 * NR];
+            cpx<T> f[NG], u[LF / 2];
         };
         auto load_g = [&](long x, cpx<T> (&f)[NG]) {
 #pragma unroll
@@ -302,9 +311,9 @@ __global__ void __launch_bounds__(SITE_BLOCK)
             const long sf = (h & 1) ? n.m[mu] : n.p[mu];
             const long sl = (h & 1) ? n.m[mu] : s;
             load_g(sf, d.f);
-            const vec2_t<T> *lp = Lin + (long)mu * 3 * NR * g.S + sl;
+            const vec2_t<T> *lp = Lin + (long)mu * (LF / 2) * g.S + sl;
 #pragma unroll
-            for (int k = 0; k < 3 * NR; ++k) d.u[k] = ld<T>(lp + (long)k * g.S);
+            for (int k = 0; k < LF / 2; ++k) d.u[k] = ld<T>(lp + (long)k * g.S);
         };
         half d[2];
         cpx<T> own[NG];
@@ -320,17 +329,15 @@ __global__ void __launch_bounds__(SITE_BLOCK)
             __builtin_amdgcn_sched_barrier(0);
             const half &cur = d[h & 1];
             const mat3<T> gn = make_g(cur.f);
-            mat3<T> u;
-#pragma unroll
-            for (int k = 0; k < 3 * NR; ++k) u.e[k / 3][k % 3] = cur.u[k];
-            if constexpr (NR == 2) rebuild_row2(u);
+            const mat3<T> u = link_from_slots<T, LF>(cur.u);
+            constexpr int PR = product_rows<LF>();
             if ((h & 1) == 0) {
-                const mat3<T> un = mul_abcd<NR>(g0, u, gn);  // g(x) U_mu(x) g(x+mu)^+
-                if constexpr (STORE) store_link<T, NR>(Lout, g.S, h >> 1, s, un);
+                const mat3<T> un = mul_abcd<PR>(g0, u, gn);  // g(x) U_mu(x) g(x+mu)^+
+                if constexpr (STORE) store_link<T, LF>(Lout, g.S, h >> 1, s, un);
                 tr += retrace(un);
                 xacc_add(X, un, T(-1));
             } else {
-                const mat3<T> umn = mul_abcd<NR>(gn, u, g0);  // g(x-mu) U_mu(x-mu) g(x)^+
+                const mat3<T> umn = mul_abcd<PR>(gn, u, g0);  // g(x-mu) U_mu(x-mu) g(x)^+
                 xacc_add(X, umn, T(1));
             }
         }
@@ -433,7 +440,7 @@ __device__ __forceinline__ mat3<double> load_G_fp64(const float2 *__restrict__ G
 }
 
 // U_mu(x) = G(x) U0_mu(x) G(x+mu)^dagger in FP64, G reunitarised in FP64
-template <int NR>
+template <int LF>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_switch(geom g, const float2 *__restrict__ G, const double2 *__restrict__ U0,
              double2 *__restrict__ L) {
@@ -444,12 +451,8 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         const mat3<double> gp = load_G_fp64(G, g.S, n.p[mu]);
-        mat3<double> u;
-        const double2 *p = U0 + ((long)mu * g.V + s) * 9;
-#pragma unroll
-        for (int k = 0; k < 3 * NR; ++k) u.e[k / 3][k % 3] = mk<double>(p[k].x, p[k].y);
-        if constexpr (NR == 2) rebuild_row2(u);
-        store_link<double, NR>(L, g.S, mu, s, mul_abcd<NR>(g0, u, gp));
+        const mat3<double> u = aos_link<double, LF>(U0 + ((long)mu * g.V + s) * 9);
+        store_link<double, LF>(L, g.S, mu, s, mul_abcd<product_rows<LF>()>(g0, u, gp));
     }
 }
 
@@ -458,7 +461,7 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 // G(x) exactly as their own site forms them, then Delta(x) and the block
 // partials of F and theta, as k_div_reduce would compute them from the stored
 // links (the same values in the same order).
-template <int NR, class TF>
+template <int LF, class TF>
 __global__ void __launch_bounds__(SITE_BLOCK)
     k_switch_div(geom g, const float2 *__restrict__ G, const double2 *__restrict__ U0,
                  double2 *__restrict__ L, vec2_t<TF> *__restrict__ D, double *__restrict__ partials) {
@@ -470,24 +473,17 @@ __global__ void __launch_bounds__(SITE_BLOCK)
         xacc<double> X;
         xacc_zero(X);
         double tr = 0;
-        auto aos = [&](int mu, long x) {
-            mat3<double> u;
-            const double2 *p = U0 + ((long)mu * g.V + x) * 9;
-#pragma unroll
-            for (int k = 0; k < 3 * NR; ++k) u.e[k / 3][k % 3] = mk<double>(p[k].x, p[k].y);
-            if constexpr (NR == 2) rebuild_row2(u);
-            return u;
-        };
+        auto aos = [&](int mu, long x) { return aos_link<double, LF>(U0 + ((long)mu * g.V + x) * 9); };
+        constexpr int PR = product_rows<LF>();
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
-            const mat3<double> un = mul_abcd<NR>(g0, aos(mu, s), load_G_fp64(G, g.S, n.p[mu]));
-            store_link<double, NR>(L, g.S, mu, s, un);
-            mat3<double> u = un;
-            if constexpr (NR == 2) rebuild_row2(u);  // as loaded back from 12 reals
+            const mat3<double> un = mul_abcd<PR>(g0, aos(mu, s), load_G_fp64(G, g.S, n.p[mu]));
+            store_link<double, LF>(L, g.S, mu, s, un);
+            const mat3<double> u = as_stored<double, LF>(un);  // as loaded back
             tr += retrace(u);
             xacc_add(X, u, -1.0);
-            mat3<double> um = mul_abcd<NR>(load_G_fp64(G, g.S, n.m[mu]), aos(mu, n.m[mu]), g0);
-            if constexpr (NR == 2) rebuild_row2(um);
+            const mat3<double> um =
+                as_stored<double, LF>(mul_abcd<PR>(load_G_fp64(G, g.S, n.m[mu]), aos(mu, n.m[mu]), g0));
             xacc_add(X, um, 1.0);
         }
         cpx<double> f0, f1, f2, f3;
@@ -817,8 +813,9 @@ hipError_t launch_pack_links(const double *Uaos, void *L, const geom &g, hipStre
     auto U = reinterpret_cast<const double2 *>(Uaos);
     auto Lp = static_cast<vec2_t<T> *>(L);
     const long V = g.V, S = g.S;
-    if (g.nr == 3) k_pack_links<T, 3><<<nblk(4 * V, 256), 256, 0, st>>>(U, Lp, V, S);
-    else k_pack_links<T, 2><<<nblk(4 * V, 256), 256, 0, st>>>(U, Lp, V, S);
+    if (g.lf == 18) k_pack_links<T, 18><<<nblk(4 * V, 256), 256, 0, st>>>(U, Lp, V, S);
+    else if (g.lf == 8) k_pack_links<T, 8><<<nblk(4 * V, 256), 256, 0, st>>>(U, Lp, V, S);
+    else k_pack_links<T, 12><<<nblk(4 * V, 256), 256, 0, st>>>(U, Lp, V, S);
     return hipGetLastError();
 }
 template hipError_t launch_pack_links<double>(const double *, void *, const geom &, hipStream_t);
@@ -829,8 +826,9 @@ hipError_t launch_unpack_links(const void *L64, double *Uaos, const geom &g, hip
     auto Lp = static_cast<const double2 *>(L64);
     auto U = reinterpret_cast<double2 *>(Uaos);
     const long V = g.V, S = g.S;
-    if (g.nr == 3) k_unpack_links<3><<<nblk(4 * V, 256), 256, 0, st>>>(Lp, U, V, S);
-    else k_unpack_links<2><<<nblk(4 * V, 256), 256, 0, st>>>(Lp, U, V, S);
+    if (g.lf == 18) k_unpack_links<18><<<nblk(4 * V, 256), 256, 0, st>>>(Lp, U, V, S);
+    else if (g.lf == 8) k_unpack_links<8><<<nblk(4 * V, 256), 256, 0, st>>>(Lp, U, V, S);
+    else k_unpack_links<12><<<nblk(4 * V, 256), 256, 0, st>>>(Lp, U, V, S);
     return hipGetLastError();
 }
 
@@ -885,11 +883,14 @@ hipError_t launch_div_reduce(const geom &g, const void *L, void *D, double *part
         auto Lp = static_cast<const vec2_t<T> *>(L);
         auto Dp = static_cast<vec2_t<TF> *>(D);
         if (g.nc == 2) return launch_div_reduce_su2<T, TF>(g, L, D, partials, status, st);
-        if (g.nr == 3)
-            k_div_reduce<T, TF, 3>
+        if (g.lf == 18)
+            k_div_reduce<T, TF, 18>
+                <<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Lp, Dp, partials, status);
+        else if (g.lf == 8)
+            k_div_reduce<T, TF, 8>
                 <<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Lp, Dp, partials, status);
         else
-            k_div_reduce<T, TF, 2>
+            k_div_reduce<T, TF, 12>
                 <<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Lp, Dp, partials, status);
         return hipGetLastError();
     });
@@ -930,14 +931,18 @@ hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void 
         };
         if constexpr (ACC) {
             // links G U0 G^dagger from the constant copy U0 (Lin), not stored
-            if (g.nr == 3) go(k_update<T, TF, true, 3, false>);
-            else go(k_update<T, TF, true, 2, false>);
-        } else if (g.nr == 3) {
-            if (exact) go(k_update<T, TF, true, 3, true>);
-            else go(k_update<T, TF, false, 3, true>);
+            if (g.lf == 18) go(k_update<T, TF, true, 18, false>);
+            else if (g.lf == 8) go(k_update<T, TF, true, 8, false>);
+            else go(k_update<T, TF, true, 12, false>);
+        } else if (g.lf == 18) {
+            if (exact) go(k_update<T, TF, true, 18, true>);
+            else go(k_update<T, TF, false, 18, true>);
+        } else if (g.lf == 8) {
+            if (exact) go(k_update<T, TF, true, 8, true>);
+            else go(k_update<T, TF, false, 8, true>);
         } else {
-            if (exact) go(k_update<T, TF, true, 2, true>);
-            else go(k_update<T, TF, false, 2, true>);
+            if (exact) go(k_update<T, TF, true, 12, true>);
+            else go(k_update<T, TF, false, 12, true>);
         }
         return hipGetLastError();
     });
@@ -1005,8 +1010,9 @@ hipError_t launch_switch(const geom &g, const void *G32, const double *U0aos, vo
     auto Gp = static_cast<const float2 *>(G32);
     auto U0 = reinterpret_cast<const double2 *>(U0aos);
     auto Lp = static_cast<double2 *>(L64);
-    if (g.nr == 3) k_switch<3><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp);
-    else k_switch<2><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp);
+    if (g.lf == 18) k_switch<18><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp);
+    else if (g.lf == 8) k_switch<8><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp);
+    else k_switch<12><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp);
     return hipGetLastError();
 }
 
@@ -1020,10 +1026,12 @@ hipError_t launch_switch_div(const geom &g, const void *G32, const double *U0aos
         auto U0 = reinterpret_cast<const double2 *>(U0aos);
         auto Lp = static_cast<double2 *>(L64);
         auto Dp = static_cast<vec2_t<TF> *>(D);
-        if (g.nr == 3)
-            k_switch_div<3, TF><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp, Dp, partials);
+        if (g.lf == 18)
+            k_switch_div<18, TF><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp, Dp, partials);
+        else if (g.lf == 8)
+            k_switch_div<8, TF><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp, Dp, partials);
         else
-            k_switch_div<2, TF><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp, Dp, partials);
+            k_switch_div<12, TF><<<site_blocks(g.V), SITE_BLOCK, 0, st>>>(g, Gp, U0, Lp, Dp, partials);
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;

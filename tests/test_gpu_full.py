@@ -129,6 +129,23 @@ def test_solve_32x4_link_format_18(lgf_gpu, configs):
     assert mu <= 1e-13 and md <= 1e-13
 
 
+def test_solve_32x4_link_format_8(lgf_gpu, configs):
+    """The minimal 8-real working links: the same solve as the 12-real form."""
+    ref = _golden()[0.45]
+    U = _config(configs, 0.45)
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, 0.08, 1e-15, max_iter=2000, link_format=8)
+    assert r.status == 0
+    out = Ug.cpu().numpy()
+    del Ug
+    assert oracle.theta(out) < 1e-15
+    assert abs(r.F - ref["F"]) <= 1e-12
+    assert abs(r.iterations - ref["iterations"]) <= 1
+    assert abs(oracle.plaquette(out) - ref["plaquette_in"]) <= 1e-12
+    mu, md = oracle.unitarity(out)
+    assert mu <= 1e-13 and md <= 1e-13
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_solve_32x4_field32(lgf_gpu, configs, precision):
     """FP64 sweeps with the Fourier field in FP32: the FP64 method's result."""

@@ -271,10 +271,89 @@ def test_link_format_18_solve(lgf_gpu, precision):
     assert abs(r12.F - r.F) < 1e-13
 
 
+# ------------------------------------------------------------ 8-real link storage
+
+def _special_links(L, seed):
+    """Links on and near the set where the usual 8-parameter form is singular
+    (|U00| = 1): diagonal links, diagonal links with their columns and rows
+    permuted (signed to stay in SU(3)), the identity, and Haar links."""
+    rng = np.random.default_rng(seed)
+    U = inputs.abelian_config(L, 2.0, seed)
+    n = U[0].size // 9
+    flat = U.reshape(4, n, 3, 3)
+    perms = [np.eye(3)[list(p)] * (1 if i % 2 == 0 else -1)  # sign keeps det = +1
+             for i, p in enumerate([(0, 1, 2), (1, 0, 2), (1, 2, 0), (0, 2, 1),
+                                    (2, 0, 1), (2, 1, 0)])]
+    pick = rng.integers(0, 6, size=(4, n))
+    for mu in range(4):
+        for j in range(n):
+            flat[mu, j] = perms[pick[mu, j]] @ flat[mu, j]
+    flat[0, ::7] = np.eye(3)
+    flat[1, ::5] = inputs.haar_su3(flat[1, ::5].shape[0], rng)
+    return U
+
+
+def test_link_format_8_round_trip(lgf_gpu):
+    """n = 0 sweeps pack the caller's links to 8 reals and back: every link is
+    reproduced to about 1e-15, on generic links and on the singular set of the
+    usual 8-real form (no link is lost)."""
+    for U in (_config_haar((4, 6, 4, 8), 5), _special_links((4, 4, 6, 4), 6)):
+        Ug = gpu(U)
+        r = lgf_gpu.iterate(Ug, ALPHA, 0, link_format=8)
+        assert r.iterations == 0
+        got = cpu(Ug)
+        full = U.copy()
+        full[..., 2, :] = np.conj(np.cross(U[..., 0, :], U[..., 1, :]))
+        assert np.max(np.abs(got - full)) < 1e-14
+        mu, md = oracle.unitarity(got)
+        assert mu < 1e-14 and md < 1e-14
+
+
+def _config_haar(L, seed):
+    return inputs.make_config(L, 0.5, seed)[0]
+
+
+@pytest.mark.parametrize("L,exact", [((4, 4, 4, 4), False), ((4, 6, 8, 12), False),
+                                     ((6, 6, 6, 6), True), ((9, 4, 6, 4), False)])
+def test_link_format_8_lockstep(lgf_gpu, L, exact):
+    U, _ = inputs.make_config(L, 0.5, 90 + sum(L))
+    for step in range(3):
+        Ug = gpu(U)
+        lgf_gpu.iterate(Ug, ALPHA, 1, exact_exp=exact, link_format=8)
+        got = cpu(Ug)
+        ref = oracle.fix(U, ALPHA, 0.0, 1, exact_exp=exact)["U"]
+        assert np.max(np.abs(got - ref)) < 1e-13, step
+        U = got
+
+
+def test_link_format_8_lockstep_special_links(lgf_gpu):
+    """One sweep from links on the singular set of the usual 8-real form."""
+    U = _special_links((4, 4, 6, 4), 7)
+    Ug = gpu(U)
+    lgf_gpu.iterate(Ug, ALPHA, 1, link_format=8)
+    ref = oracle.fix(U, ALPHA, 0.0, 1)["U"]
+    assert np.max(np.abs(cpu(Ug) - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_link_format_8_solve(lgf_gpu, precision):
+    U, _ = inputs.make_config((8, 8, 8, 8), 0.5, inputs.CONFIG_SEEDS[("8^4", 0.5)])
+    ref = oracle.fix(U, ALPHA, 1e-14, 1000)
+    Ug = gpu(U)
+    r = lgf_gpu.fix(Ug, ALPHA, 1e-14, precision=precision, max_iter=1000, link_format=8)
+    assert r.status == 0
+    _check_solution(cpu(Ug), U, 1e-14, r.F)
+    assert abs(r.F - ref["F"]) < 1e-12
+    if precision == "fp64":
+        assert abs(r.iterations - ref["iterations"]) <= 1
+    else:
+        assert 0 < r.fp32_iterations < r.iterations <= ref["iterations"] + 2
+
+
 def test_link_format_rejects_other_sizes(lgf_gpu):
     U = gpu(inputs.unit_config((4, 4, 4, 4)))
     c = lgf_gpu._ctx(U)
-    for bad in (8, 9, 0, 24):
+    for bad in (7, 9, 0, 24):
         with pytest.raises(lgf_gpu.LgfError):
             c.set_link_format(bad)
     r = c.fix(U, ALPHA, 1e-15, 10)

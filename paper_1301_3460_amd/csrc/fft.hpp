@@ -39,6 +39,17 @@ __host__ __device__ constexpr int fft_reg_span(int n) {
     return n <= 32 ? n : n / fft_split(n);
 }
 
+// Register tier of an extent: the kernels that transform along a runtime
+// extent are instantiated per tier, and an instance's register allocation is
+// that of the heaviest transform it holds.  Tier 16: one-pass extents up to
+// 16 and two-pass extents N1 x N2 with N1 <= 8, N2 <= 12 (36 = 6x6,
+// 48 = 6x8, 54 = 6x9, 64 = 8x8, 72 = 8x9, 96 = 8x12), which fit 128 VGPRs
+// in every pass kernel; tier 32: the rest.
+__host__ __device__ constexpr int fft_tier(int n) {
+    return n <= 32 ? (n <= 16 ? 16 : 32)
+                   : ((fft_split(n) <= 8 && n / fft_split(n) <= 12) ? 16 : 32);
+}
+
 __host__ __device__ constexpr bool fft_supported(int n) {
     if (n < 2 || n > FFT_MAX_EXTENT) return false;
     int m = n;
@@ -296,7 +307,7 @@ LGF_HD void lds_axis_fsi(int n, vec2_t<T> *lds, int ncols, int stride, Base base
     switch (n) {
 #define LGF_CASE(NN)                                                                   \
     case NN:                                                                           \
-        if constexpr (fft_reg_span(NN) <= RMAX)                                        \
+        if constexpr (fft_tier(NN) <= RMAX)                                            \
             lds_axis_fsi_n<NN, T>(lds, ncols, stride, base, prep, scale, tw);          \
         break;
         LGF_FFT_EXTENTS(LGF_CASE)
@@ -305,16 +316,16 @@ LGF_HD void lds_axis_fsi(int n, vec2_t<T> *lds, int ncols, int stride, Base base
     }
 }
 
-// Runtime-extent dispatch over the extents whose register span is at most
-// RMAX: a kernel's register allocation is that of its largest case, so a
-// kernel instantiated for spans up to 16 runs at a higher occupancy.
+// Runtime-extent dispatch over the extents of register tier at most RMAX
+// (fft_tier): a kernel's register allocation is that of its largest case, so
+// a kernel instantiated for tier 16 runs at a higher occupancy.
 template <int DIR, class T, int RMAX, class Base>
 LGF_HD void lds_axis_fft(int n, vec2_t<T> *lds, int ncols, int stride, Base base,
                          const vec2_t<T> *__restrict__ tw) {
     switch (n) {
 #define LGF_CASE(NN)                                                                   \
     case NN:                                                                           \
-        if constexpr (fft_reg_span(NN) <= RMAX)                                        \
+        if constexpr (fft_tier(NN) <= RMAX)                                            \
             lds_axis_fft_n<NN, DIR, T>(lds, ncols, stride, base, tw);                  \
         break;
         LGF_FFT_EXTENTS(LGF_CASE)

@@ -62,7 +62,7 @@ constexpr int XY_BLOCK = 256;
 // an x pass and a y pass
 constexpr size_t XY_PLANE_LDS_MAX = 160 * 1024;
 
-// RMAX: largest register span (fft_reg_span) of the extents this instance handles
+// RMAX: largest register tier (fft_tier) of the extents this instance handles
 template <class T, int DIR, int RMAX>
 __global__ void __launch_bounds__(XY_BLOCK)
     k_fft_xy(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
@@ -152,9 +152,10 @@ constexpr int ZT_PAD = 4;
 // longer at 48^3 x 96.
 constexpr size_t AXIS_TILE_BYTES = 32 * 1024;
 
-// Register budgets: 128 VGPRs for spans up to 16 (four waves per SIMD, the
+
+// Register budgets: 128 VGPRs for tier 16 (four waves per SIMD, the
 // occupancy the 32 KB tiles allow; the fused scaled round trip would take
-// 129), 256 for the wider spans (without the hint it spills to AGPRs).
+// 129), 256 for tier 32 (without the hint it spills to AGPRs).
 template <class T, int MODE, int RMAX>
 __global__ void __launch_bounds__(AXIS_BLOCK) __attribute__((amdgpu_waves_per_eu(RMAX <= 16 ? 4 : 2)))
     k_fft_axis(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ twa,
@@ -166,16 +167,17 @@ __global__ void __launch_bounds__(AXIS_BLOCK) __attribute__((amdgpu_waves_per_eu
     const int N = ap.N, W = ap.W, PW = ap.PW, PB = ap.PB;
     const long s0 = (long)xcd_block(blockIdx.x, gridDim.x) * W;
     const int Wt = (int)min((long)W, ap.R - s0);
-    const int o0 = blockIdx.y * ap.B;  // first slice
-    const int Bt = min(ap.B, ap.nslice - o0);
+    const int o0 = blockIdx.y * ap.B;  // first slice (B divides the slice count)
     vec2_t<T> *F = D + (long)blockIdx.z * g.S + s0 + (long)o0 * ap.sb;
+    // offsets inside one field are below 2^31 (the volume is)
+    const unsigned sj = (unsigned)ap.sj, sb = (unsigned)ap.sb;
     const int nel = W * N * ap.B;
     for (int i = threadIdx.x; i < nel; i += AXIS_BLOCK) {
         const int w = i % W, r = i / W, j = r % N, b = r / N;
         vec2_t<T> v;
         v.x = 0;
         v.y = 0;
-        if (w < Wt && b < Bt) v = F[(long)j * ap.sj + (long)b * ap.sb + w];
+        if (w < Wt) v = F[(unsigned)j * sj + (unsigned)b * sb + (unsigned)w];
         lds[b * PB + j * PW + w] = v;
     }
     __syncthreads();
@@ -190,7 +192,7 @@ __global__ void __launch_bounds__(AXIS_BLOCK) __attribute__((amdgpu_waves_per_eu
         auto prep = [=](int c) -> T {
             const int w = c % W, b = c / W;
             const long sxy = s0 + w;
-            if (sxy >= Lxy || b >= Bt) return T(-1);
+            if (sxy >= Lxy) return T(-1);
             const int y = (int)(sxy / g.Lx), x = (int)(sxy - (long)y * g.Lx);
             return (px[x] + py[y]) + pz[o0 + b];
         };
@@ -202,7 +204,7 @@ __global__ void __launch_bounds__(AXIS_BLOCK) __attribute__((amdgpu_waves_per_eu
     __syncthreads();
     for (int i = threadIdx.x; i < nel; i += AXIS_BLOCK) {
         const int w = i % W, r = i / W, j = r % N, b = r / N;
-        if (w < Wt && b < Bt) F[(long)j * ap.sj + (long)b * ap.sb + w] = lds[b * PB + j * PW + w];
+        if (w < Wt) F[(unsigned)j * sj + (unsigned)b * sb + (unsigned)w] = lds[b * PB + j * PW + w];
     }
 }
 
@@ -557,7 +559,7 @@ hipError_t launch_axis(const geom &g, vec2_t<T> *D, const vec2_t<T> *twa, const 
                        T p2max_over_V, const axis_plan &a, const dev_status *status,
                        hipStream_t st) {
     const dim3 grid = axis_grid(a, g.nf);
-    if (fft_reg_span(a.N) <= 16)
+    if (fft_tier(a.N) <= 16)
         k_fft_axis<T, MODE, 16><<<grid, AXIS_BLOCK, a.lds, st>>>(g, D, twa, ptab, p2max_over_V, a,
                                                                  status);
     else
@@ -601,7 +603,7 @@ hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const 
         return launch_axis<T, 1>(g, Dp, twp, nullptr, zero, pl.x, status, st);
     }
     dim3 grid((unsigned)(g.Lz * g.Lt), (unsigned)g.nf);
-    if (fft_reg_span(g.Lx) <= 16 && fft_reg_span(g.Ly) <= 16) {
+    if (fft_tier(g.Lx) <= 16 && fft_tier(g.Ly) <= 16) {
         if (dir < 0) k_fft_xy<T, -1, 16><<<grid, XY_BLOCK, pl.lds_xy, st>>>(g, Dp, twp, status);
         else k_fft_xy<T, +1, 16><<<grid, XY_BLOCK, pl.lds_xy, st>>>(g, Dp, twp, status);
     } else {
@@ -636,7 +638,7 @@ hipError_t launch_fft_xy_inv_acc(const geom &g, void *D, const void *tw, const f
     if (pl.xy == 1) {
         const size_t b = xy_acc_lds_bytes<T>(g);
         const dim3 grid((unsigned)(g.Lz * g.Lt));
-        const bool sm = fft_reg_span(g.Lx) <= 16 && fft_reg_span(g.Ly) <= 16;
+        const bool sm = fft_tier(g.Lx) <= 16 && fft_tier(g.Ly) <= 16;
 #define LGF_XG(R, E) k_fft_xy_acc<T, R, E><<<grid, XY_BLOCK, b, st>>>(g, Dp, twp, Go, Gn, c, status)
         if (sm) {
             if (exact) LGF_XG(16, true);

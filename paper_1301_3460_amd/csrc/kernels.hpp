@@ -120,7 +120,7 @@ hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void 
 struct axis_plan {
     int N = 0;           // extent of the axis
     int W = 1, B = 1;    // inner elements and slices per block
-    int nslice = 1;      // slices in total (the last group may be ragged)
+    int nslice = 1;      // slices in total (a multiple of B)
     int PW = 1, PB = 1;  // LDS strides of an axis position and of a slice
     long R = 1;          // length of the inner range (the last row may be ragged)
     long sj = 0, sb = 0; // HBM strides of the axis and of a slice, in elements

@@ -40,9 +40,9 @@ SD_TOL = 1e-10  # plain steepest descent needs thousands of sweeps at 32^4
 # algorithmic bytes per site of each sweep kernel: FP64, and the FP32 sweeps
 # of a mixed solve, whose inverse (x,y) pass also does G <- g G (R field 32,
 # R+W G 96, the field itself not written back) and whose update forms the
-# links from the input copy U0 (R U0 192, R G 48, W field 32).  On planes
-# wider than 32 the accumulation is a kernel of its own after a plain inverse
-# pass (64 + 32 + 96).
+# links from the input copy U0 (R U0 192, R G 48, W field 32).  Where a plane
+# of all four fields does not fit one block (fp32_acc_fused), the accumulation
+# is a kernel of its own after a plain inverse pass (64 + 32 + 96).
 BYTES_PER_SITE = {
     "fp64": {"fft_xy_fwd": 128, "fft_zt": 128, "fft_xy_inv": 128, "update": 896, "finalize": 0},
     "fp32": {"fft_xy_fwd": 64, "fft_zt": 64, "fft_xy_inv": 128, "update": 272, "finalize": 0},
@@ -59,6 +59,16 @@ BYTES_THETA_GRAD = 384 + 64 + 256 + 256
 UPDATE_SOURCES = ("paper_1301_3460_amd/csrc/sweep.hip", "paper_1301_3460_amd/csrc/common.hpp",
                   "paper_1301_3460_amd/csrc/su3.hpp", "paper_1301_3460_amd/csrc/kernels.hpp")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "update_32x4_fp64_traffic.json")
+
+
+def fp32_acc_fused(L) -> bool:
+    """Whether the FP32 sweeps accumulate G inside the inverse (x,y) pass: a
+    register-column plane (both extents up to 32) or a plane of all four FP32
+    fields within 150 KB of LDS (the library's rule)."""
+    Lx, Ly = L[0], L[1]
+    if Lx <= 32 and Ly <= 32:
+        return 4 * Lx <= 512
+    return Ly * (Lx + 1) * 8 <= 160 * 1024 and 4 * Ly * (Lx + 1) * 8 <= 150 * 1024
 
 
 def log(*a):
@@ -164,6 +174,8 @@ def main() -> int:
                          "the 32^4 link field (a known-size reference for HBM counters)")
     ap.add_argument("--autograd-only", action="store_true",
                     help="only the forward+backward timing of the differentiable forms")
+    ap.add_argument("--link-format", type=int, choices=(8, 12, 18), default=12,
+                    help="with --sweeps-only: reals per working link of the timed FP64 sweeps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -226,6 +238,11 @@ def main() -> int:
 
     ctx64 = lgf.Context(Lrun, "fp64")
     ctx32 = lgf.Context(Lrun, "mixed")
+    if args.link_format != 12:
+        if not args.sweeps_only:
+            print("--link-format applies to --sweeps-only runs", file=sys.stderr)
+            return 2
+        ctx64.set_link_format(args.link_format)
 
     # ---- sweep throughput (the headline value), after W warmup sweeps
     work.copy_(U0)
@@ -245,16 +262,19 @@ def main() -> int:
     prof32 = ctx32.profile(U0, ALPHA, 50)
     per_kernel = {}
     fp32_bytes = dict(BYTES_PER_SITE["fp32"])
-    if Lrun[0] > 32 or Lrun[1] > 32:
+    if not fp32_acc_fused(Lrun):
         fp32_bytes["fft_xy_inv"] = BYTES_XY_INV_ACC_SEPARATE
-    for name, prof, nbytes in (("fp64", prof64, BYTES_PER_SITE["fp64"]), ("fp32", prof32, fp32_bytes)):
+    fp64_bytes = dict(BYTES_PER_SITE["fp64"])
+    fp64_bytes["update"] = {12: fp64_bytes["update"], 18: BYTES_UPDATE_18,
+                            8: BYTES_UPDATE_8}[args.link_format]
+    for name, prof, nbytes in (("fp64", prof64, fp64_bytes), ("fp32", prof32, fp32_bytes)):
         per_kernel[name] = {
             k: {"ms": round(v, 5),
                 "GBps": round(nbytes[k] * V / (v * 1e-3) / 1e9, 1) if v > 0 else None}
             for k, v in prof.items()}
     log("per-kernel:", json.dumps(per_kernel))
     upd_ms = prof64["update"]
-    achieved = BYTES_PER_SITE["fp64"]["update"] * V / (upd_ms * 1e-3) / 1e9
+    achieved = fp64_bytes["update"] * V / (upd_ms * 1e-3) / 1e9
 
     if args.sweeps_only:
         # reference copy kernel: reads and writes exactly work.numel()*16 bytes

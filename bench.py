@@ -421,6 +421,7 @@ def main() -> int:
     c2m.close()
     del U2, w2
 
+    cpu48 = None
     # 48^3 x 96: radix-3 and two-pass transform extents; every working set far
     # beyond the 256 MB Infinity Cache, so HBM rates are not flattered by it
     if not args.no_large:
@@ -463,6 +464,19 @@ def main() -> int:
             log(f"48^3x96 solve {prec}: {entry}")
         c48m.close()
         c48.close()
+        if not args.no_cpu:
+            # the oracle on this host at 48^3 x 96: a bounded sample of sweeps
+            import oracle
+
+            oracle.set_threads(len(os.sched_getaffinity(0)))
+            Uh48 = U48.cpu().numpy()
+            t0 = time.perf_counter()
+            oracle.iterate(Uh48, ALPHA, 2)
+            c48s = (time.perf_counter() - t0) / 2
+            cpu48 = {"sweeps": 2, "s_per_sweep": round(c48s, 3),
+                     "gpu_speedup_fp64_sweeps": round(c48s * ips48, 1)}
+            log(f"cpu oracle 48^3x96: {cpu48}")
+            del Uh48
         del U48, w48
         torch.cuda.empty_cache()
 
@@ -506,6 +520,8 @@ def main() -> int:
             cpu["time_to_theta_F"] = ref["F"]
             cpu["gpu_speedup_time_to_theta_fp64"] = round(1e3 * cs / t64, 1)
             log(f"cpu oracle solve: {cs:.1f} s, {ref['iterations']} sweeps")
+        if cpu48 is not None:
+            cpu["sample_48x3x96"] = cpu48
 
     out = {
         "metric": METRIC,

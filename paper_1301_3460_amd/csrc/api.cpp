@@ -339,13 +339,15 @@ geom g12(const lgf_ctx *c) {
 
 // (Re)allocate the working link buffers for the context's link format: each
 // holds 4 links x (lf/2 for SU(3), 2 for SU(2)) complex entries per site
-// (FP64); the FP32 pair aliases the second buffer.
+// (FP64), and never fewer than the 12-real form needs, because the per-step
+// entry points pack 12-real links into buffer 0 whatever the format; the
+// FP32 pair aliases the second buffer.
 bool alloc_links(lgf_ctx *c) {
     for (auto &p : c->L64) {
         if (p) (void)hipFree(p);
         p = nullptr;
     }
-    const size_t n = (size_t)4 * (c->g.nc == 2 ? 2 : c->g.lf / 2) * c->g.S;
+    const size_t n = (size_t)4 * (c->g.nc == 2 ? 2 : std::max(c->g.lf, 12) / 2) * c->g.S;
     for (auto &p : c->L64)
         if (hipMalloc((void **)&p, n * sizeof(double2)) != hipSuccess) return false;
     c->L32[0] = reinterpret_cast<float2 *>(c->L64[1]);
@@ -361,11 +363,13 @@ int check_ctx(lgf_ctx *c) {
     return LGF_OK;
 }
 
-// Pack caller links into FP64 working buffer 0, then F/theta of them.
+// Pack caller links into FP64 working buffer 0 (12-real form), then F/theta
+// of them.
 int eval_links64(lgf_ctx *c, const double *U, double &F, double &theta) {
-    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], c->g, c->stream));
+    const geom g = g12(c);
+    HIPCHK(c, launch_pack_links<double>(U, c->L64[0], g, c->stream));
     HIPCHK(c, launch_status_reset(c->status, 0, c->stream));
-    HIPCHK(c, launch_div_reduce<double>(c->g, c->L64[0], c->D64[0], c->partials, c->status,
+    HIPCHK(c, launch_div_reduce<double>(g, c->L64[0], c->D64[0], c->partials, c->status,
                                         finp(c, false), c->stream));
     HIPCHK(c, launch_reduce_only(c->partials, c->nparts, c->reduce_out, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->reduce_host, c->reduce_out, 2 * sizeof(double),

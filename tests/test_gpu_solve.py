@@ -350,6 +350,27 @@ def test_link_format_8_solve(lgf_gpu, precision):
         assert 0 < r.fp32_iterations < r.iterations <= ref["iterations"] + 2
 
 
+@pytest.mark.parametrize("nreal", [8, 18])
+def test_link_format_leaves_per_step_entry_points_12_real(lgf_gpu, nreal):
+    """The per-step entry points pack 12-real links into the context's link
+    buffer whatever the format set for fix/iterate, so the buffers hold at
+    least the 12-real form (an 8-real context once overflowed them)."""
+    L = (6, 6, 6, 4)
+    U, _ = inputs.make_config(L, 0.5, 95)
+    c = lgf_gpu.Context(L, "fp64")
+    c.set_link_format(nreal)
+    Ug = gpu(U)
+    r = c.iterate(Ug, ALPHA, 2)
+    assert r.iterations == 2
+    V = cpu(Ug)
+    D = cpu(c.divergence(Ug))
+    assert np.max(np.abs(D - oracle.delta(V))) < 1e-13
+    assert c.theta(Ug) == pytest.approx(oracle.theta(V), rel=1e-12)
+    assert c.functional(Ug) == pytest.approx(oracle.F(V), abs=1e-14)
+    assert c.plaquette(Ug) == pytest.approx(oracle.plaquette(V), abs=1e-13)
+    c.close()
+
+
 def test_link_format_rejects_other_sizes(lgf_gpu):
     U = gpu(inputs.unit_config((4, 4, 4, 4)))
     c = lgf_gpu._ctx(U)

@@ -64,7 +64,8 @@ struct lgf_ctx {
     double *partials = nullptr;
     int nparts = 0;
     dev_status *status = nullptr;
-    dev_status *status_host = nullptr;  // pinned
+    dev_status *status_host = nullptr;  // pinned, 3 slots: synchronous reads, two batches
+    hipEvent_t batch_ev[2] = {nullptr, nullptr};  // a batch's status copy has landed
     double *reduce_out = nullptr;       // device [2]
     double *reduce_host = nullptr;      // pinned [2]
     double *histF = nullptr, *histT = nullptr;
@@ -273,47 +274,90 @@ int read_status(lgf_ctx *c, dev_status &out) {
 // after n = st.n sweeps and `st` holds the final state.
 // prepared: the status reset and the first divergence with its stopping test
 // were enqueued by the caller (the mixed hand-over fuses them).
+//
+// Sweeps go to the stream in batches.  After each batch the device status is
+// copied to a pinned host slot (two slots, alternating, each with an event),
+// and the next batch is enqueued before the host waits for the previous
+// one's status, so the device does not idle while the host decides: a solve
+// sizes each batch from the contraction rate last observed, counting the
+// sweeps still in flight; once the stopping test has fired, sweeps still in
+// flight find the device flag set and return at once.  A fixed count of
+// sweeps (tol <= 0) goes in batches of 64.
 template <class T>
 int run_phase(lgf_ctx *c, double alpha, double tol, int max_iter, int hist_base, dev_status &st,
               int stall = 0, bool prepared = false) {
-    using P = prec<T>;
     if (!prepared) {
         HIPCHK(c, launch_status_reset(c->status, hist_base, c->stream));
-        HIPCHK(c, launch_div_reduce<T>(c->g, P::links(c, 0), P::field(c, 0), c->partials,
-                                       c->status, finp(c, true, tol, max_iter, 0, stall),
-                                       c->stream));
+        HIPCHK(c, launch_div_reduce<T>(c->g, prec<T>::links(c, 0), prec<T>::field(c, 0),
+                                       c->partials, c->status,
+                                       finp(c, true, tol, max_iter, 0, stall), c->stream));
     }
     int rc = read_status(c, st);
     if (rc) return rc;
     const T half_alpha = (T)(0.5 * alpha);
     c->half_alpha = 0.5 * alpha;
-    int enq = 0;  // sweeps enqueued so far
-    double th_prev = st.theta;
+    const fin_params fp = finp(c, true, tol, max_iter, 1, stall);
+    int enq = 0;              // sweeps enqueued so far
+    double th_prev = st.theta;  // the observation before the last one (rate)
     int n_prev = st.n;
-    while (!st.done) {
-        // sweeps to enqueue before the next status read: a fixed count (tol
-        // <= 0) goes in batches of 64; a solve predicts the sweeps still needed
-        // from the observed contraction rate (clamped before the conversion)
+    // sweeps to enqueue next, from the last observed state and the sweeps
+    // enqueued beyond it.  A solve caps its batches at max(8, n/4): the
+    // contraction rate of the accelerated method rises several-fold in its
+    // last decades, so a prediction from the rate so far overshoots, and every
+    // sweep enqueued past the stop still costs its (empty) launches; with two
+    // batches in flight, small batches cost no idle time.
+    auto next_batch = [&]() {
         int k = tol > 0 ? 4 : 64;
         if (tol > 0 && st.n > n_prev && st.theta > 0 && th_prev > 0) {
             double rate = std::pow(st.theta / th_prev, 1.0 / (double)(st.n - n_prev));
             rate = std::min(std::max(rate, 1e-3), 0.95);
-            const double need = std::log(tol / st.theta) / std::log(rate);
+            const double need = std::log(tol / st.theta) / std::log(rate) - (double)(enq - st.n);
             k = (int)std::ceil(std::min(std::max(need, 1.0), 64.0));
+            k = std::min(k, std::max(8, st.n / 4));
         }
         k = std::max(1, std::min(k, 64));
-        k = std::min(k, max_iter - enq);
-        if (k <= 0) k = 1;  // the finalize of the last sweep sets done
-        th_prev = st.theta;
-        n_prev = st.n;
+        return std::min(k, max_iter - enq);
+    };
+    auto enqueue_batch = [&](int k, int slot) -> int {
         for (int i = 0; i < k; ++i) {
             const int cur = (enq + i) & 1;
-            HIPCHK(c, enqueue_sweep<T>(c, cur, half_alpha, finp(c, true, tol, max_iter, 1, stall)));
+            HIPCHK(c, enqueue_sweep<T>(c, cur, half_alpha, fp));
         }
         enq += k;
-        rc = read_status(c, st);
-        if (rc) return rc;
+        HIPCHK(c, hipMemcpyAsync(c->status_host + 1 + slot, c->status, sizeof(dev_status),
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipEventRecord(c->batch_ev[slot], c->stream));
+        return LGF_OK;
+    };
+    int queued = 0, observed = 0;  // batches enqueued / whose status was read
+    while (!st.done) {
+        // keep two batches in flight: enqueue the next one (at least one
+        // sweep, so the device is never idle before the stop) unless every
+        // allowed sweep is already enqueued
+        if (queued - observed < 2) {
+            const int k = next_batch();
+            if (k > 0) {
+                if ((rc = enqueue_batch(k, queued & 1))) return rc;
+                ++queued;
+                continue;
+            }
+        }
+        if (observed == queued) {
+            // nothing in flight and no sweep left to enqueue: the last
+            // sweep's test must have ended the phase; read it
+            rc = read_status(c, st);
+            if (rc) return rc;
+            if (!st.done) return fail(c, LGF_ERR_DEVICE, "sweep count exhausted without a stop");
+            break;
+        }
+        HIPCHK(c, hipEventSynchronize(c->batch_ev[observed & 1]));
+        th_prev = st.theta;
+        n_prev = st.n;
+        st = c->status_host[1 + (observed & 1)];
+        ++observed;
     }
+    // sweeps enqueued after the stop return at once; let them drain
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return LGF_OK;
 }
 
@@ -555,7 +599,9 @@ int lgf_create_group(lgf_ctx **out, const int L[4], int nc, int precision, void 
     ok = ok && alloc((void **)&c->reduce_out, 2 * sizeof(double));
     ok = ok && alloc((void **)&c->histF, HIST_CAP * sizeof(double));
     ok = ok && alloc((void **)&c->histT, HIST_CAP * sizeof(double));
-    ok = ok && hipHostMalloc((void **)&c->status_host, sizeof(dev_status), 0) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&c->status_host, 3 * sizeof(dev_status), 0) == hipSuccess;
+    for (auto &ev : c->batch_ev)
+        ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->reduce_host, 2 * sizeof(double), 0) == hipSuccess;
     if (!ok) {
         lgf_destroy(c);
@@ -599,6 +645,8 @@ void lgf_destroy(lgf_ctx *c) {
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (c->status_host) (void)hipHostFree(c->status_host);
+    for (auto ev : c->batch_ev)
+        if (ev) (void)hipEventDestroy(ev);
     if (c->reduce_host) (void)hipHostFree(c->reduce_host);
     delete c;
 }

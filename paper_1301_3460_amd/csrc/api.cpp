@@ -539,6 +539,7 @@ bool fft_plan_fits(const fft_plan &p) {
     };
     if (p.xy != 2 && p.lds_xy > LDS_MAX) return false;
     if (p.xy == 2 && !(axis_ok(p.x) && axis_ok(p.y))) return false;
+    if (p.zt2 && p.lds_zt2 > LDS_MAX) return false;
     if (p.rc) return p.lds <= LDS_MAX;
     return axis_ok(p.z) && axis_ok(p.t);
 }
@@ -562,8 +563,8 @@ int lgf_create_group(lgf_ctx **out, const int L[4], int nc, int precision, void 
                     "2^31 sites)");
     {
         const geom g0 = make_geom(L, nc);
-        if (!fft_plan_fits(plan_fft<double>(g0, ZT_LDS_BUDGET)) ||
-            !fft_plan_fits(plan_fft<float>(g0, ZT_LDS_BUDGET)))
+        if (!fft_plan_fits(plan_fft<double>(g0, ZT_LDS_BUDGET, 0)) ||
+            !fft_plan_fits(plan_fft<float>(g0, ZT_LDS_BUDGET, 0)))
             return fail(nullptr, LGF_ERR_ARG, "lattice extent: transform passes exceed the "
                                               "LDS or grid limits");
     }
@@ -620,8 +621,11 @@ int lgf_create_group(lgf_ctx **out, const int L[4], int nc, int precision, void 
     if (e == hipSuccess) e = hipMemcpy(c->tw32, tw32.data(), nt * sizeof(float2), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->pt64, pt64.data(), nt * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->pt32, pt32.data(), nt * sizeof(float), hipMemcpyHostToDevice);
-    c->plan64 = plan_fft<double>(c->g, ZT_LDS_BUDGET);
-    c->plan32 = plan_fft<float>(c->g, ZT_LDS_BUDGET);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
+        ncu = 0;  // no two-tile passes
+    c->plan64 = plan_fft<double>(c->g, ZT_LDS_BUDGET, ncu);
+    c->plan32 = plan_fft<float>(c->g, ZT_LDS_BUDGET, ncu);
     // best effort: a launch that still exceeds the limit reports its own error
     fft_set_max_lds<double>(c->g, c->plan64);
     fft_set_max_lds<float>(c->g, c->plan32);

@@ -407,6 +407,145 @@ __global__ void __launch_bounds__(rc_max_threads<T>())
 }
 
 // ---------------------------------------------------------------------------
+// Two-tile register-column passes (FP64, 32 x 32).
+//
+// A block of the kernels above moves one tile: it loads it, transforms it
+// through LDS and stores it.  A 32-point FP64 column pins a wave to its SIMD
+// alone (registers and LDS), and with two such rounds of blocks per compute
+// unit the loads, the arithmetic and the stores of a round run one after the
+// other.  Here a block takes tiles k and k + G (G blocks, half the tile
+// count, so that every compute unit still holds two): the second tile's
+// columns are loaded into registers (the accumulation registers take what
+// does not fit) while the first tile goes through its LDS phase, inverse
+// transform and stores.  The momentum table is copied into LDS, so the
+// column phase issues no vector-memory load whose wait would also drain the
+// prefetch.  Every tile goes through the same operations as in the one-tile
+// kernels: the results are bitwise identical.
+// ---------------------------------------------------------------------------
+
+constexpr int RC2_N = 32;  // both register-column extents of the two-tile passes
+constexpr int RC2_ZT_W = 4;  // xy-sites per (z,t) tile (64-byte rows)
+constexpr int RC2_XY_F = 4;  // fields per (x,y) tile (all of an SU(3) plane)
+
+template <int N>
+__device__ __forceinline__ void load_column(const double2 *p, unsigned stride,
+                                            cpx<double> (&a)[N]) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) a[j] = ld<double>(p + j * stride);
+}
+
+template <int N>
+__device__ __forceinline__ void store_column(double2 *p, unsigned stride, const cpx<double> (&a)[N]) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) st<double>(p + j * stride, a[j]);
+}
+
+// (z,t): tile k = W consecutive xy-sites of field k / (Lxy / W); thread
+// (w, z) holds the t-column of site s0 + w at z.  MODE 0 only.
+template <int NZ, int NT, int W, class Hook>
+__device__ __forceinline__ void zt2_tile(const geom &g, int s0, cpx<double> (&a)[NT], Hook prefetch,
+                                         vec2_t<double> *lds, const vec2_t<double> *twz,
+                                         const vec2_t<double> *twt, const double *pz,
+                                         double p2max_over_V) {
+    using T = double;
+    constexpr int PJ = NZ * W + ZT_PAD;
+    const int w = threadIdx.x % W, z = threadIdx.x / W;
+    const T *q = reinterpret_cast<const T *>(lds + NT * PJ);
+    const T *qx = q, *qy = q + g.Lx, *qt = q + g.Lx + g.Ly + NZ;
+    const int Lx = g.Lx;
+    auto base = [](int c) { return (c / W) * PJ + (c % W); };  // c = w + W*j
+    dft<NT, -1>(a, twt);
+    auto col = [&](int c0, int C) {
+        auto prep = [=](int c) -> T {
+            const int sxy = s0 + (c % W);  // the tiles are whole
+            const int y = sxy / Lx, x = sxy - y * Lx;
+            return (qx[x] + qy[y]) + qt[c0 + c / W];
+        };
+        auto scale = [=](T b, int k) -> T { return fa_factor<T>(b, pz[k], p2max_over_V); };
+        prefetch();
+        col_fwd_scale_inv_n<NZ, T>(lds, W * C, W, base, prep, scale, twz);
+    };
+    exchange_axis<NT, T>(a, w, z, W, 1, PJ, lds, col);
+    dft<NT, +1>(a, twt);
+}
+
+template <int NZ, int NT, int W>
+__global__ void __launch_bounds__(NZ * W) __attribute__((amdgpu_waves_per_eu(1, 1)))
+    k_fft_zt_rc2(geom g, vec2_t<double> *__restrict__ D, const vec2_t<double> *__restrict__ tw,
+                 const double *__restrict__ ptab, double p2max_over_V,
+                 const dev_status *__restrict__ status) {
+    if (status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    vec2_t<double> *lds = reinterpret_cast<vec2_t<double> *>(smem_raw);
+    {
+        double *q = reinterpret_cast<double *>(lds + NT * (NZ * W + ZT_PAD));
+        const int n = g.Lx + g.Ly + NZ + NT;
+        for (int i = threadIdx.x; i < n; i += NZ * W) q[i] = ptab[i];
+    }
+    const unsigned Lxy = (unsigned)g.Lx * (unsigned)g.Ly, ts = (unsigned)NZ * Lxy;
+    const int ntx = (int)(Lxy / W), G = gridDim.x;
+    const int w = threadIdx.x % W, z = threadIdx.x / W;
+    const int k0 = xcd_block(blockIdx.x, G), k1 = k0 + G;
+    const int f0 = k0 / ntx, f1 = k1 / ntx;
+    const int s0 = (k0 - f0 * ntx) * W, s1 = (k1 - f1 * ntx) * W;
+    vec2_t<double> *p0 = D + (long)f0 * g.S + (unsigned)z * Lxy + (unsigned)(s0 + w);
+    vec2_t<double> *p1 = D + (long)f1 * g.S + (unsigned)z * Lxy + (unsigned)(s1 + w);
+    const vec2_t<double> *twz = tw_z<double>(g, tw), *twt = tw_t<double>(g, tw);
+    const double *pz = ptab + g.Lx + g.Ly;
+    cpx<double> a[NT], b[NT];
+    load_column<NT>(p0, ts, a);
+    zt2_tile<NZ, NT, W>(g, s0, a, [&] { load_column<NT>(p1, ts, b); }, lds, twz, twt, pz,
+                        p2max_over_V);
+    __syncthreads();  // every thread has read its column of the first tile back
+    store_column<NT>(p0, ts, a);
+    zt2_tile<NZ, NT, W>(g, s1, b, [] {}, lds, twz, twt, pz, p2max_over_V);
+    store_column<NT>(p1, ts, b);
+}
+
+// (x,y): tile k = plane k of all F fields; thread (f, x) holds a y-column.
+template <int NX, int NY, int F, int DIR, class Hook>
+__device__ __forceinline__ void xy2_tile(cpx<double> (&a)[NY], Hook prefetch, vec2_t<double> *lds,
+                                         const vec2_t<double> *twx, const vec2_t<double> *twy) {
+    using T = double;
+    constexpr int SW = NX + 1, PJ = F * SW;
+    const int x = threadIdx.x % NX, fl = threadIdx.x / NX;
+    auto base = [](int c) { return (c / F) * PJ + (c % F) * SW; };  // c = fl + F*j
+    auto col = [&](int, int C) {
+        prefetch();
+        lds_axis_fft_n<NX, DIR, T>(lds, F * C, 1, base, twx);
+    };
+    if (DIR < 0) {
+        dft<NY, -1>(a, twy);
+        exchange_axis<NY, T>(a, fl, x, 1, SW, PJ, lds, col);
+    } else {
+        exchange_axis<NY, T>(a, fl, x, 1, SW, PJ, lds, col);
+        dft<NY, +1>(a, twy);
+    }
+}
+
+template <int NX, int NY, int F, int DIR>
+__global__ void __launch_bounds__(NX * F) __attribute__((amdgpu_waves_per_eu(1, 1)))
+    k_fft_xy_rc2(geom g, vec2_t<double> *__restrict__ D, const vec2_t<double> *__restrict__ tw,
+                 const dev_status *__restrict__ status) {
+    if (status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    vec2_t<double> *lds = reinterpret_cast<vec2_t<double> *>(smem_raw);
+    const int x = threadIdx.x % NX, fl = threadIdx.x / NX;
+    const int k0 = blockIdx.x, k1 = k0 + gridDim.x;
+    constexpr unsigned Lxy = (unsigned)NX * NY;
+    vec2_t<double> *p0 = D + (long)fl * g.S + (unsigned)k0 * Lxy + x;
+    vec2_t<double> *p1 = D + (long)fl * g.S + (unsigned)k1 * Lxy + x;
+    const vec2_t<double> *twy = tw_y<double>(g, tw);
+    cpx<double> a[NY], b[NY];
+    load_column<NY>(p0, NX, a);
+    xy2_tile<NX, NY, F, DIR>(a, [&] { load_column<NY>(p1, NX, b); }, lds, tw, twy);
+    __syncthreads();  // every thread has read its column of the first tile back
+    store_column<NY>(p0, NX, a);
+    xy2_tile<NX, NY, F, DIR>(b, [] {}, lds, tw, twy);
+    store_column<NY>(p1, NX, b);
+}
+
+// ---------------------------------------------------------------------------
 // planning and launchers
 // ---------------------------------------------------------------------------
 
@@ -467,7 +606,21 @@ template <class T> axis_plan plan_axis(const geom &g, int ax) {
     return a;
 }
 
-template <class T> fft_plan plan_fft(const geom &g, size_t zt_lds_budget) {
+// Two-tile passes: FP64, both extents 32, whole tiles, an even tile count
+// of at least four per compute unit.
+template <class T> void plan_two_tile(const geom &g, int ncu, fft_plan &p) {
+    if (!std::is_same<T, double>::value || ncu <= 0) return;
+    const long Lxy = (long)g.Lx * g.Ly;
+    auto enough = [&](long tiles) { return tiles % 2 == 0 && tiles / 2 >= 2L * ncu; };
+    p.xy2 = p.xy == 0 && g.Lx == RC2_N && g.Ly == RC2_N && g.nf == RC2_XY_F &&
+            xy_fields_per_block<T>(g) == RC2_XY_F && enough((long)g.Lz * g.Lt);
+    p.zt2 = p.rc && g.Lz == RC2_N && g.Lt == RC2_N && p.W == RC2_ZT_W && Lxy % RC2_ZT_W == 0 &&
+            enough(Lxy / RC2_ZT_W * g.nf);
+    if (p.zt2)
+        p.lds_zt2 = p.lds + (size_t)(g.Lx + g.Ly + g.Lz + g.Lt) * sizeof(T);
+}
+
+template <class T> fft_plan plan_fft(const geom &g, size_t zt_lds_budget, int ncu) {
     fft_plan p{};
     const size_t e = sizeof(vec2_t<T>);
     if (g.Lx <= 32 && g.Ly <= 32) {
@@ -493,6 +646,7 @@ template <class T> fft_plan plan_fft(const geom &g, size_t zt_lds_budget) {
             p.rc = true;
             p.W = W;
             p.lds = rc_bytes(W);
+            plan_two_tile<T>(g, ncu, p);
             return p;
         }
     }
@@ -501,6 +655,7 @@ template <class T> fft_plan plan_fft(const geom &g, size_t zt_lds_budget) {
     p.t = plan_axis<T>(g, 3);
     p.W = p.z.W;
     p.lds = std::max(p.z.lds, p.t.lds);
+    plan_two_tile<T>(g, ncu, p);
     return p;
 }
 
@@ -545,6 +700,14 @@ template <class T> void fft_set_max_lds(const geom &g, const fft_plan &p) {
             set(reinterpret_cast<const void *>(&k_fft_xy_acc<T, 32, false>), b);
         }
     }
+    if constexpr (std::is_same<T, double>::value) {
+        if (p.xy2) {
+            set(reinterpret_cast<const void *>(&k_fft_xy_rc2<RC2_N, RC2_N, RC2_XY_F, -1>), p.lds_xy);
+            set(reinterpret_cast<const void *>(&k_fft_xy_rc2<RC2_N, RC2_N, RC2_XY_F, 1>), p.lds_xy);
+        }
+        if (p.zt2)
+            set(reinterpret_cast<const void *>(&k_fft_zt_rc2<RC2_N, RC2_N, RC2_ZT_W>), p.lds_zt2);
+    }
     if (p.xy == 1) {
         set(reinterpret_cast<const void *>(&k_fft_xy<T, -1, 16>), p.lds_xy);
         set(reinterpret_cast<const void *>(&k_fft_xy<T, 1, 16>), p.lds_xy);
@@ -573,6 +736,17 @@ hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const 
                          const dev_status *status, hipStream_t st) {
     auto Dp = static_cast<vec2_t<T> *>(D);
     auto twp = static_cast<const vec2_t<T> *>(tw);
+    if constexpr (std::is_same<T, double>::value) {
+        if (pl.xy2) {
+            const unsigned G = (unsigned)(g.Lz * g.Lt / 2);
+            constexpr unsigned nt = RC2_N * RC2_XY_F;
+            if (dir < 0)
+                k_fft_xy_rc2<RC2_N, RC2_N, RC2_XY_F, -1><<<G, nt, pl.lds_xy, st>>>(g, Dp, twp, status);
+            else
+                k_fft_xy_rc2<RC2_N, RC2_N, RC2_XY_F, 1><<<G, nt, pl.lds_xy, st>>>(g, Dp, twp, status);
+            return hipGetLastError();
+        }
+    }
     if (pl.xy == 0) {
         const int F = xy_fields_per_block<T>(g);
         dim3 grid((unsigned)(g.Lz * g.Lt), (unsigned)(g.nf / F));
@@ -675,6 +849,14 @@ hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const
     const long Lxy = (long)g.Lx * g.Ly;
     auto Dp = static_cast<vec2_t<T> *>(D);
     auto twp = static_cast<const vec2_t<T> *>(tw);
+    if constexpr (std::is_same<T, double>::value) {
+        if (pl.zt2 && mode == 0) {
+            const unsigned G = (unsigned)(Lxy / RC2_ZT_W * g.nf / 2);
+            k_fft_zt_rc2<RC2_N, RC2_N, RC2_ZT_W><<<G, RC2_N * RC2_ZT_W, pl.lds_zt2, st>>>(
+                g, Dp, twp, ptab, p2max_over_V, status);
+            return hipGetLastError();
+        }
+    }
     if (pl.rc) {
         const int W = pl.W;
         dim3 grid((unsigned)((Lxy + W - 1) / W), (unsigned)g.nf);

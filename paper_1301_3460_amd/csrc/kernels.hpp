@@ -138,8 +138,14 @@ struct fft_plan {
     int W = 1;
     size_t lds = 0;
     axis_plan x, y, z, t;
+    // FP64 32 x 32 register-column passes with two tiles per block (the
+    // scaled (z,t) round trip and both (x,y) directions), where half the
+    // tile count still gives every compute unit two blocks
+    bool xy2 = false, zt2 = false;
+    size_t lds_zt2 = 0;
 };
-template <class T> fft_plan plan_fft(const geom &g, size_t zt_lds_budget);
+// ncu: compute units of the device (0: no two-tile passes)
+template <class T> fft_plan plan_fft(const geom &g, size_t zt_lds_budget, int ncu);
 // every kernel of the plan fits the LDS of a compute unit and its grid limits
 bool fft_plan_fits(const fft_plan &p);
 template <class T> void fft_set_max_lds(const geom &g, const fft_plan &p);

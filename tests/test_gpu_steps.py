@@ -80,6 +80,23 @@ def test_fft4d(lgf_gpu, L, sign):
         assert np.max(np.abs(got - ref2)) < 1e-13 * scale
 
 
+# FP64 32 x 32 register-column passes that take two tiles per block (enough
+# planes or xy-sites for two blocks per compute unit at half the tile count):
+# both (x,y) and (z,t) at 32^4, the (x,y) pass alone, the (z,t) pass alone.
+TWO_TILE_SHAPES = [(32, 32, 32, 32), (32, 32, 16, 64), (64, 32, 32, 32)]
+
+
+@pytest.mark.parametrize("L", TWO_TILE_SHAPES)
+@pytest.mark.parametrize("sign", [-1, +1])
+def test_fft4d_two_tile(lgf_gpu, L, sign):
+    test_fft4d(lgf_gpu, L, sign)
+
+
+@pytest.mark.parametrize("L", TWO_TILE_SHAPES)
+def test_fourier_accelerate_two_tile(lgf_gpu, L):
+    test_fourier_accelerate(lgf_gpu, L)
+
+
 @pytest.mark.parametrize("L", SHAPES)
 def test_fourier_accelerate(lgf_gpu, L):
     U = _config(L, 200 + sum(L))

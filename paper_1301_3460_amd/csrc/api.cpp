@@ -629,6 +629,7 @@ int lgf_create_group(lgf_ctx **out, const int L[4], int nc, int precision, void 
     // best effort: a launch that still exceeds the limit reports its own error
     fft_set_max_lds<double>(c->g, c->plan64);
     fft_set_max_lds<float>(c->g, c->plan32);
+    update_set_max_lds();
     if (e != hipSuccess) {
         std::string m = std::string("initialisation failed: ") + hipGetErrorString(e);
         lgf_destroy(c);

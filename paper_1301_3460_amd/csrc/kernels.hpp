@@ -149,6 +149,9 @@ template <class T> fft_plan plan_fft(const geom &g, size_t zt_lds_budget, int nc
 // every kernel of the plan fits the LDS of a compute unit and its grid limits
 bool fft_plan_fits(const fft_plan &p);
 template <class T> void fft_set_max_lds(const geom &g, const fft_plan &p);
+// LDS limit of the FP32 update that shares links through LDS (once per process
+// and device is enough; repeating it is harmless)
+void update_set_max_lds();
 // Twiddle tables: one buffer per real type with the axis tables
 // exp(-2 pi i j / L_mu), j < L_mu, of x, y, z and t one after the other.
 // (x,y) transform, dir -1 forward, +1 inverse

@@ -352,6 +352,206 @@ __global__ void __launch_bounds__(SITE_BLOCK)
     block_sum2<SITE_BLOCK>(fs, ts, partials, blockIdx.x);
 }
 
+// ---------------------------------------------------------------------------
+// FP32 sweeps of an SU(3) mixed solve with the links shared through LDS
+// ---------------------------------------------------------------------------
+
+// Every link U_mu(x) enters two divergences: with sign - at x and with sign +
+// at x + mu, so k_update forms each link twice.  The divergence is linear in
+// the links through P(M): the off-diagonal differences M_ij - conj(M_ji)
+// (i < j) and the traceless part of 2 Im M_ii, 8 reals, in the order of the 4
+// Fourier-field entries.  This kernel forms the 4 links leaving each site,
+// keeps their P in LDS and takes the links arriving from x - mu from LDS when
+// x - mu is in the block, forming them again otherwise.  A block holds
+// UPDS_XY consecutive xy-sites at UPDS_T consecutive t and one z: the x
+// neighbour is in the block whenever UPDS_XY is a multiple of Lx, the y
+// neighbour except in the block's first xy-row, the t neighbour except at
+// its first t, the z neighbour never.  FP32 arithmetic as in k_update; the
+// per-link projections change the rounding order of the sums, not the
+// quantities.  Partial sums go out per group of SITE_BLOCK threads, so the
+// finalize reads the same number of partials as after k_update.
+constexpr int UPDS_XY = 256, UPDS_T = 4, UPDS_THREADS = UPDS_XY * UPDS_T;
+constexpr size_t UPDS_LDS = (size_t)8 * 4 * UPDS_THREADS * sizeof(float);
+
+inline bool update_shared_ok(const geom &g) {
+    const long Lxy = (long)g.Lx * g.Ly;
+    return g.nc == 3 && g.lf == 12 && Lxy % UPDS_XY == 0 && g.Lt % UPDS_T == 0;
+}
+
+// a += sgn * P(m)
+template <class T> LGF_HD void proj_add(T (&a)[8], const mat3<T> &m, T sgn) {
+    a[0] += sgn * (m.e[0][1].re - m.e[1][0].re);
+    a[1] += sgn * (m.e[0][1].im + m.e[1][0].im);
+    a[2] += sgn * (m.e[0][2].re - m.e[2][0].re);
+    a[3] += sgn * (m.e[0][2].im + m.e[2][0].im);
+    a[4] += sgn * (m.e[1][2].re - m.e[2][1].re);
+    a[5] += sgn * (m.e[1][2].im + m.e[2][1].im);
+    const T d0 = T(2) * m.e[0][0].im, d1 = T(2) * m.e[1][1].im, d2 = T(2) * m.e[2][2].im;
+    const T tr = (d0 + d1 + d2) * T(1.0 / 3.0);
+    a[6] += sgn * (d0 - tr);
+    a[7] += sgn * (d1 - tr);
+}
+
+// P(m) alone
+template <class T> LGF_HD void proj_of(T (&a)[8], const mat3<T> &m) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = T(0);
+    proj_add(a, m, T(1));
+}
+
+// block sum of two doubles per group of NG threads into partials[2 * (slot0 + group) + {0,1}]
+template <int NT, int NG>
+__device__ __forceinline__ void group_sum2(double a, double b, double *partials, int slot0) {
+    static_assert(NT % NG == 0 && NG % 64 == 0, "wave64 groups");
+    __shared__ double sa[NT / 64], sb[NT / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sa[w] = a;
+        sb[w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x % NG == 0) {
+        const int w0 = threadIdx.x >> 6;
+        double A = 0, B = 0;
+#pragma unroll
+        for (int i = 0; i < NG / 64; ++i) {
+            A += sa[w0 + i];
+            B += sb[w0 + i];
+        }
+        const int slot = slot0 + threadIdx.x / NG;
+        partials[2 * slot] = A;
+        partials[2 * slot + 1] = B;
+    }
+}
+
+__global__ void __launch_bounds__(UPDS_THREADS)
+    k_update_shared32(geom g, const float2 *__restrict__ Lin, const float2 *__restrict__ GX,
+                      float2 *__restrict__ Dout, double *__restrict__ partials,
+                      const dev_status *__restrict__ status) {
+    using T = float;
+    if (status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    T *P = reinterpret_cast<T *>(smem_raw);  // P[(k * 4 + mu) * UPDS_THREADS + i]
+    // block -> (z fastest, then the xy group, then the t group); XCDs walk
+    // contiguous ranges
+    const int B = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned Lxy = (unsigned)g.Lx * (unsigned)g.Ly, ngxy = Lxy / UPDS_XY;
+    const unsigned z = (unsigned)B % (unsigned)g.Lz, r = (unsigned)B / (unsigned)g.Lz;
+    const unsigned xy0 = (r % ngxy) * UPDS_XY, t0 = (r / ngxy) * UPDS_T;
+    const int i = threadIdx.x;  // local index: (t - t0) * UPDS_XY + (xy - xy0)
+    const unsigned xy = xy0 + (unsigned)i % UPDS_XY, t = t0 + (unsigned)i / UPDS_XY;
+    const unsigned s = xy + Lxy * (z + (unsigned)g.Lz * t);
+    const unsigned x = xy % (unsigned)g.Lx, y = (xy / (unsigned)g.Lx) % (unsigned)g.Ly;
+    const unsigned Lx = g.Lx, Ly = g.Ly, Lz = g.Lz, Lt = g.Lt, sz = Lxy, st = Lxy * Lz;
+    // neighbour s + mu (fwd) or s - mu, periodic, in 32-bit arithmetic (V < 2^31)
+    auto nb = [&](int mu, bool fwd) -> unsigned {
+        if (mu == 0) return fwd ? (x == Lx - 1 ? s - (Lx - 1) : s + 1) : (x == 0 ? s + (Lx - 1) : s - 1);
+        if (mu == 1)
+            return fwd ? (y == Ly - 1 ? s - (Ly - 1) * Lx : s + Lx) : (y == 0 ? s + (Ly - 1) * Lx : s - Lx);
+        if (mu == 2)
+            return fwd ? (z == Lz - 1 ? s - (Lz - 1) * sz : s + sz) : (z == 0 ? s + (Lz - 1) * sz : s - sz);
+        return fwd ? (t == Lt - 1 ? s - (Lt - 1) * st : s + st) : (t == 0 ? s + (Lt - 1) * st : s - st);
+    };
+    const long S = g.S;
+    auto load_g = [&](unsigned q, cpx<T> (&f)[6]) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) f[k] = ld<T>(GX + (long)k * S + q);
+    };
+    auto make_g = [&](const cpx<T> (&f)[6]) {
+        mat3<T> m;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) m.e[k / 3][k % 3] = f[k];
+        rebuild_row2(m);
+        return m;
+    };
+    struct half {
+        cpx<T> f[6], u[6];
+    };
+    // h = 2 mu + b as in k_update: b = 0 the link leaving x, b = 1 the one arriving from x - mu
+    auto fetch = [&](int h, half &d) {
+        const int mu = h >> 1;
+        const unsigned sf = nb(mu, (h & 1) == 0);
+        const unsigned sl = (h & 1) ? sf : s;
+        load_g(sf, d.f);
+        const float2 *lp = Lin + (long)mu * 6 * S + sl;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) d.u[k] = ld<T>(lp + (long)k * S);
+    };
+    cpx<T> own[6];
+    load_g(s, own);
+    half d[2];
+    fetch(0, d[0]);
+    const mat3<T> g0 = make_g(own);
+    T X[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) X[k] = T(0);
+    T tr = 0;
+    // links leaving x: U_mu(x) = g(x) U0_mu(x) g(x+mu)^+; the z link arriving
+    // from x - z (never in the block) is fetched during the last of them
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        fetch(mu < 3 ? 2 * (mu + 1) : 5, d[(mu + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        const half &cur = d[mu & 1];
+        const mat3<T> un = mul_abcd<2>(g0, link_from_slots<T, 12>(cur.u), make_g(cur.f));
+        tr += retrace(un);
+        T pm[8];
+        proj_of(pm, un);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            P[(k * 4 + mu) * UPDS_THREADS + i] = pm[k];
+            X[k] -= pm[k];
+        }
+    }
+    // the z link arriving from x - z: g(x-z) U0_z(x-z) g(x)^+
+    {
+        const half &cur = d[0];
+        const mat3<T> umn = mul_abcd<2>(make_g(cur.f), link_from_slots<T, 12>(cur.u), g0);
+        proj_add(X, umn, T(1));
+    }
+    __syncthreads();
+    // x, y, t links arriving from x - mu: from LDS inside the block
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        if (mu == 2) continue;
+        unsigned txy = xy, tt = t;
+        if (mu == 0) txy = x == 0 ? xy + Lx - 1 : xy - 1;
+        if (mu == 1) txy = y == 0 ? xy + (Ly - 1) * Lx : xy - Lx;
+        if (mu == 3) tt = t == 0 ? Lt - 1 : t - 1;
+        const unsigned lx = txy - xy0, lt = tt - t0;
+        if (lx < (unsigned)UPDS_XY && lt < (unsigned)UPDS_T) {
+            const int j = (int)(lt * UPDS_XY + lx);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) X[k] += P[(k * 4 + mu) * UPDS_THREADS + j];
+        } else {
+            half e;
+            fetch(2 * mu + 1, e);
+            const mat3<T> umn = mul_abcd<2>(make_g(e.f), link_from_slots<T, 12>(e.u), g0);
+            proj_add(X, umn, T(1));
+        }
+    }
+    const cpx<T> f0 = mk<T>(X[0], X[1]), f1 = mk<T>(X[2], X[3]), f2 = mk<T>(X[4], X[5]),
+                 f3 = mk<T>(X[6], X[7]);
+    const T da = X[6], db = X[7];
+    const T th = T(2) * (norm2(f0) + norm2(f1) + norm2(f2)) + da * da + db * db + (da + db) * (da + db);
+    st_stream<T>(Dout + s, f0);
+    st_stream<T>(Dout + S + s, f1);
+    st_stream<T>(Dout + 2 * S + s, f2);
+    st_stream<T>(Dout + 3 * S + s, f3);
+    group_sum2<UPDS_THREADS, SITE_BLOCK>((double)tr, (double)th, partials,
+                                         blockIdx.x * (UPDS_THREADS / SITE_BLOCK));
+}
+
+void update_set_max_lds() {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_shared32),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)UPDS_LDS);
+}
+
 // reorder 4 fields between natural index order and transform-position order
 __global__ void k_reorder(geom g, const double2 *__restrict__ in, long si, double2 *__restrict__ out,
                           long so, int to_natural) {
@@ -931,6 +1131,12 @@ hipError_t launch_update(const geom &g, const void *Lin, void *Lout, const void 
         };
         if constexpr (ACC) {
             // links G U0 G^dagger from the constant copy U0 (Lin), not stored
+            if (update_shared_ok(g)) {
+                k_update_shared32<<<(unsigned)(g.V / UPDS_THREADS), UPDS_THREADS, UPDS_LDS, st>>>(
+                    g, static_cast<const float2 *>(Lin), static_cast<const float2 *>(GX),
+                    static_cast<float2 *>(Dout), partials, status);
+                return hipGetLastError();
+            }
             if (g.lf == 18) go(k_update<T, TF, true, 18, false>);
             else if (g.lf == 8) go(k_update<T, TF, true, 8, false>);
             else go(k_update<T, TF, true, 12, false>);

@@ -127,10 +127,15 @@ def test_bad_arguments_raise(lgf_gpu):
 
 # the FP32 sweeps' kernels by plane shape: register columns with G accumulated
 # in the inverse (x,y) pass (8 and 32 wide), the 4-field LDS kernel for wider
-# planes with register spans up to 16 (48 wide) and 32 (Ly = 48 beside Lx = 32)
+# planes with register spans up to 16 (48 wide) and 32 (Ly = 48 beside Lx = 32);
+# the update that shares links through LDS (xy-planes of a multiple of 256
+# sites, Lt a multiple of 4): x rows inside a block (32, 16 wide), rows that
+# straddle blocks (48 wide), two rows per block (128 wide), Lz = 3
 @pytest.mark.parametrize("L,seed", [((8, 8, 8, 8), 35), ((32, 8, 4, 4), 36), ((48, 4, 4, 6), 37),
                                     ((32, 48, 2, 2), 38), ((27, 9, 4, 6), 39),
-                                    ((256, 48, 2, 2), 40)])
+                                    ((256, 48, 2, 2), 40), ((16, 16, 3, 4), 41),
+                                    ((48, 16, 2, 4), 42), ((128, 4, 2, 4), 43),
+                                    ((32, 32, 4, 8), 44)])
 def test_mixed_iterate_applies_accumulated_transformation(lgf_gpu, L, seed):
     """FP32-phase lockstep: a mixed-precision context runs FP32 sweeps and
     applies the accumulated transformation to the FP64 input, so the result is

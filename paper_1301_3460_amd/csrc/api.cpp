@@ -301,7 +301,7 @@ int run_phase(lgf_ctx *c, double alpha, double tol, int max_iter, int hist_base,
     double th_prev = st.theta;  // the observation before the last one (rate)
     int n_prev = st.n;
     // sweeps to enqueue next, from the last observed state and the sweeps
-    // enqueued beyond it.  A solve caps its batches at max(8, n/4): the
+    // enqueued beyond it.  A solve caps its batches at max(4, n/8): the
     // contraction rate of the accelerated method rises several-fold in its
     // last decades, so a prediction from the rate so far overshoots, and every
     // sweep enqueued past the stop still costs its (empty) launches; with two
@@ -313,7 +313,7 @@ int run_phase(lgf_ctx *c, double alpha, double tol, int max_iter, int hist_base,
             rate = std::min(std::max(rate, 1e-3), 0.95);
             const double need = std::log(tol / st.theta) / std::log(rate) - (double)(enq - st.n);
             k = (int)std::ceil(std::min(std::max(need, 1.0), 64.0));
-            k = std::min(k, std::max(8, st.n / 4));
+            k = std::min(k, std::max(4, st.n / 8));
         }
         k = std::max(1, std::min(k, 64));
         return std::min(k, max_iter - enq);

@@ -209,6 +209,83 @@ __global__ void __launch_bounds__(AXIS_BLOCK) __attribute__((amdgpu_waves_per_eu
 }
 
 // ---------------------------------------------------------------------------
+// Two-axis LDS tiles (tile2_plan).  With an extent above 32 in (z,t) the
+// transform is split as (x,t) planes and (y,z) tiles instead: the first and
+// last passes hold whole (x,t) planes of one field (rows of Lx contiguous
+// sites), the middle pass holds W consecutive x-sites x the (y,z) plane and
+// runs the forward transforms, the scaling and the inverse transforms.  Three
+// passes over the field instead of five.
+// MODE -1: a forward then b forward; +1: b inverse then a inverse; 0: a
+// forward, b forward / scaling / b inverse, a inverse.
+// ---------------------------------------------------------------------------
+
+// block size of the two-axis tiles: two blocks of this size share a compute
+// unit (the LDS tile), so the lighter register tier takes twice the threads
+template <class T, int MODE, int RMAX, int NTHR>
+__global__ void __launch_bounds__(NTHR)
+    k_fft_tile2(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,
+                const T *__restrict__ ptab, T p2max_over_V, tile2_plan tp,
+                const dev_status *__restrict__ status) {
+    if (status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
+    // inner groups of one outer slice are consecutive on one XCD (they share lines)
+    const int B = xcd_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int grp = B % tp.ngrp, outer = B / tp.ngrp;
+    const int W = tp.W, Na = tp.Na, Nb = tp.Nb, PA = tp.PA, PB = tp.PB;
+    const long i0 = (long)grp * W;
+    const int Wt = (int)min((long)W, tp.R - i0);
+    vec2_t<T> *F = D + (long)blockIdx.z * g.S + i0 + (long)outer * tp.so;
+    // offsets inside one field are below 2^31 (the volume is)
+    const unsigned sa = (unsigned)tp.sa, sb = (unsigned)tp.sb;
+    const int nel = W * Na * Nb;
+    for (int i = threadIdx.x; i < nel; i += NTHR) {
+        const int w = i % W, r = i / W, ja = r % Na, jb = r / Na;
+        vec2_t<T> v;
+        v.x = 0;
+        v.y = 0;
+        if (w < Wt) v = F[(unsigned)ja * sa + (unsigned)jb * sb + (unsigned)w];
+        lds[w + ja * PA + jb * PB] = v;
+    }
+    __syncthreads();
+    const vec2_t<T> *twa = tw + tp.ta, *twb = tw + tp.tb;
+    auto cola = [W, PB](int c) { return (c % W) + (c / W) * PB; };  // c = w + W*jb
+    auto colb = [W, PA](int c) { return (c % W) + (c / W) * PA; };  // c = w + W*ja
+    if (MODE <= 0) {
+        lds_axis_fft<-1, T, RMAX>(Na, lds, W * Nb, PA, cola, twa);
+        __syncthreads();
+    }
+    if (MODE == 0) {
+        const T *pa = ptab + tp.ta, *pb = ptab + tp.tb, *pw = ptab + tp.tw, *po = ptab + tp.to;
+        const long R = tp.R;
+        // per column c = w + W*ja along b: p2 without the b term, or -1 for a
+        // padding column of a ragged group (factor 0)
+        auto prep = [=](int c) -> T {
+            const int w = c % W, ja = c / W;
+            if (i0 + w >= R) return T(-1);
+            return (pa[ja] + pw[i0 + w]) + po[outer];
+        };
+        auto scale = [=](T base, int k) -> T { return fa_factor<T>(base, pb[k], p2max_over_V); };
+        lds_axis_fsi<T, RMAX>(Nb, lds, W * Na, PB, colb, prep, scale, twb);
+        __syncthreads();
+    } else if (MODE < 0) {
+        lds_axis_fft<-1, T, RMAX>(Nb, lds, W * Na, PB, colb, twb);
+        __syncthreads();
+    } else {
+        lds_axis_fft<1, T, RMAX>(Nb, lds, W * Na, PB, colb, twb);
+        __syncthreads();
+    }
+    if (MODE >= 0) {
+        lds_axis_fft<1, T, RMAX>(Na, lds, W * Nb, PA, cola, twa);
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < nel; i += NTHR) {
+        const int w = i % W, r = i / W, ja = r % Na, jb = r / Na;
+        if (w < Wt) F[(unsigned)ja * sa + (unsigned)jb * sb + (unsigned)w] = lds[w + ja * PA + jb * PB];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Register-column transforms (register-axis extent up to 32).
 //
 // Each thread keeps the whole column of one strided lattice axis (t for the
@@ -620,6 +697,57 @@ template <class T> void plan_two_tile(const geom &g, int ncu, fft_plan &p) {
         p.lds_zt2 = p.lds + (size_t)(g.Lx + g.Ly + g.Lz + g.Lt) * sizeof(T);
 }
 
+// (x,t) planes and (y,z) tiles of TILE2_W x-sites (FP64, an extent above 32
+// in (z,t)), where both tiles fit the budget and rows are at least 16 sites.
+constexpr int TILE2_W = 2;
+template <class T> void plan_tile2(const geom &g, size_t budget, fft_plan &p) {
+    if (!std::is_same<T, double>::value || p.rc) return;
+    const size_t e = sizeof(vec2_t<T>);
+    const long Lxy = (long)g.Lx * g.Ly, Lxyz = Lxy * g.Lz;
+    const int ox = 0, oy = g.Lx, oz = g.Lx + g.Ly, ot = g.Lx + g.Ly + g.Lz;
+    tile2_plan a;  // (x,t) planes: a = x (the rows), b = t; slices (y,z)
+    a.Na = g.Lx;
+    a.Nb = g.Lt;
+    a.W = 1;
+    a.sa = 1;
+    a.sb = Lxyz;
+    a.R = 1;
+    a.ngrp = 1;
+    a.nouter = g.Ly * g.Lz;
+    a.so = g.Lx;
+    a.PA = 1;
+    a.PB = g.Lx + 1;
+    a.ta = ox;
+    a.tb = ot;
+    a.rmax = std::max(fft_tier(g.Lx), fft_tier(g.Lt));
+    a.lds = (size_t)a.Nb * a.PB * e;
+    a.nthr = a.lds > 80 * 1024 ? 1024 : 512;
+    tile2_plan b;  // (y,z) tiles: W x-sites, a = y, b = z; slices t
+    b.Na = g.Ly;
+    b.Nb = g.Lz;
+    b.W = TILE2_W;
+    b.sa = g.Lx;
+    b.sb = Lxy;
+    b.R = g.Lx;
+    b.ngrp = (g.Lx + TILE2_W - 1) / TILE2_W;
+    b.nouter = g.Lt;
+    b.so = Lxyz;
+    b.PA = TILE2_W;
+    b.PB = g.Ly * TILE2_W + 1;
+    b.ta = oy;
+    b.tb = oz;
+    b.tw = ox;
+    b.to = ot;
+    b.rmax = std::max(fft_tier(g.Ly), fft_tier(g.Lz));
+    b.lds = (size_t)b.Nb * b.PB * e;
+    b.nthr = b.lds > 80 * 1024 ? 1024 : 512;
+    if (g.Lx < 16 || a.lds > budget || b.lds > 160 * 1024 || a.nouter > 65535) return;
+    p.t2 = true;
+    p.xy2 = false;  // the (x,t) planes replace the (x,y) pass
+    p.t2a = a;
+    p.t2b = b;
+}
+
 template <class T> fft_plan plan_fft(const geom &g, size_t zt_lds_budget, int ncu) {
     fft_plan p{};
     const size_t e = sizeof(vec2_t<T>);
@@ -656,7 +784,26 @@ template <class T> fft_plan plan_fft(const geom &g, size_t zt_lds_budget, int nc
     p.W = p.z.W;
     p.lds = std::max(p.z.lds, p.t.lds);
     plan_two_tile<T>(g, ncu, p);
+    plan_tile2<T>(g, zt_lds_budget, p);
     return p;
+}
+
+inline dim3 tile2_grid(const tile2_plan &a, int nf) {
+    return dim3((unsigned)a.ngrp, (unsigned)a.nouter, (unsigned)nf);
+}
+
+template <class T, int MODE>
+hipError_t launch_tile2(const geom &g, vec2_t<T> *D, const vec2_t<T> *tw, const T *ptab,
+                        T p2max_over_V, const tile2_plan &a, const dev_status *status,
+                        hipStream_t st) {
+    const dim3 grid = tile2_grid(a, g.nf);
+#define LGF_T2(R, N)                                                                               \
+    k_fft_tile2<T, MODE, R, N><<<grid, N, a.lds, st>>>(g, D, tw, ptab, p2max_over_V, a, status)
+    if (a.rmax > 16) LGF_T2(32, 256);
+    else if (a.nthr == 1024) LGF_T2(16, 1024);
+    else LGF_T2(16, 512);
+#undef LGF_T2
+    return hipGetLastError();
 }
 
 inline dim3 axis_grid(const axis_plan &a, int nf) {
@@ -700,6 +847,15 @@ template <class T> void fft_set_max_lds(const geom &g, const fft_plan &p) {
             set(reinterpret_cast<const void *>(&k_fft_xy_acc<T, 32, false>), b);
         }
     }
+    if (p.t2) {
+        const size_t b = std::max(p.t2a.lds, p.t2b.lds);
+#define LGF_T2S(M)                                                                   \
+    set(reinterpret_cast<const void *>(&k_fft_tile2<T, M, 16, 512>), b);            \
+    set(reinterpret_cast<const void *>(&k_fft_tile2<T, M, 16, 1024>), b);           \
+    set(reinterpret_cast<const void *>(&k_fft_tile2<T, M, 32, 256>), b);
+        LGF_T2S(-1) LGF_T2S(0) LGF_T2S(1)
+#undef LGF_T2S
+    }
     if constexpr (std::is_same<T, double>::value) {
         if (p.xy2) {
             set(reinterpret_cast<const void *>(&k_fft_xy_rc2<RC2_N, RC2_N, RC2_XY_F, -1>), p.lds_xy);
@@ -736,6 +892,11 @@ hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const 
                          const dev_status *status, hipStream_t st) {
     auto Dp = static_cast<vec2_t<T> *>(D);
     auto twp = static_cast<const vec2_t<T> *>(tw);
+    if (pl.t2) {
+        // (x,t) planes: forward first, inverse last
+        if (dir < 0) return launch_tile2<T, -1>(g, Dp, twp, nullptr, T(0), pl.t2a, status, st);
+        return launch_tile2<T, 1>(g, Dp, twp, nullptr, T(0), pl.t2a, status, st);
+    }
     if constexpr (std::is_same<T, double>::value) {
         if (pl.xy2) {
             const unsigned G = (unsigned)(g.Lz * g.Lt / 2);
@@ -856,6 +1017,12 @@ hipError_t launch_fft_zt(const geom &g, void *D, int mode, const void *tw, const
                 g, Dp, twp, ptab, p2max_over_V, status);
             return hipGetLastError();
         }
+    }
+    if (pl.t2) {
+        // (y,z) tiles: forward, scaled round trip or inverse
+        if (mode == 0) return launch_tile2<T, 0>(g, Dp, twp, ptab, p2max_over_V, pl.t2b, status, st);
+        if (mode < 0) return launch_tile2<T, -1>(g, Dp, twp, ptab, p2max_over_V, pl.t2b, status, st);
+        return launch_tile2<T, 1>(g, Dp, twp, ptab, p2max_over_V, pl.t2b, status, st);
     }
     if (pl.rc) {
         const int W = pl.W;

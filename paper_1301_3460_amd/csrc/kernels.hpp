@@ -126,6 +126,23 @@ struct axis_plan {
     long sj = 0, sb = 0; // HBM strides of the axis and of a slice, in elements
     size_t lds = 0;      // LDS bytes per block
 };
+// A pass over two axes a and b held together in LDS: per block W consecutive
+// inner elements (HBM stride 1) x Na x Nb, one inner group and one outer
+// slice; the LDS element (w, ja, jb) is at w + ja*PA + jb*PB.
+struct tile2_plan {
+    int Na = 0, Nb = 0, W = 1;
+    long sa = 0, sb = 0;     // HBM strides of axes a and b, in elements
+    long R = 1;              // inner extent (the last group may be ragged)
+    int ngrp = 1;            // inner groups (R / W rounded up)
+    int nouter = 1;          // outer slices
+    long so = 0;             // HBM stride of an outer slice
+    int PA = 1, PB = 1;      // LDS strides along a and b
+    int ta = 0, tb = 0;      // offsets of the axis tables of a and b (twiddles, p2)
+    int tw = 0, to = 0;      // offsets of the p2 tables of the inner and the outer axis
+    int rmax = 16;           // register tier of the larger of Na, Nb
+    int nthr = 512;          // threads per block (1024 when one block fills a compute unit)
+    size_t lds = 0;          // LDS bytes per block
+};
 // How the 4D transform of a context is split into passes.
 struct fft_plan {
     // (x,y): 0 register-column kernel (both extents up to 32), 1 whole plane in
@@ -143,6 +160,12 @@ struct fft_plan {
     // tile count still gives every compute unit two blocks
     bool xy2 = false, zt2 = false;
     size_t lds_zt2 = 0;
+    // FP64, (z,t) beyond the register columns: (x,t) planes as the first and
+    // last pass (t2a) and (y,z) tiles of W x-sites as the middle pass (t2b),
+    // three passes over the field instead of the five of the x,y / z / t / z /
+    // x,y scheme
+    bool t2 = false;
+    tile2_plan t2a, t2b;
 };
 // ncu: compute units of the device (0: no two-tile passes)
 template <class T> fft_plan plan_fft(const geom &g, size_t zt_lds_budget, int ncu);

@@ -82,8 +82,35 @@ def test_fft4d(lgf_gpu, L, sign):
 
 # FP64 32 x 32 register-column passes that take two tiles per block (enough
 # planes or xy-sites for two blocks per compute unit at half the tile count):
-# both (x,y) and (z,t) at 32^4, the (x,y) pass alone, the (z,t) pass alone.
-TWO_TILE_SHAPES = [(32, 32, 32, 32), (32, 32, 16, 64), (64, 32, 32, 32)]
+# both (x,y) and (z,t) at 32^4, the (z,t) pass alone (64-wide planes in LDS).
+TWO_TILE_SHAPES = [(32, 32, 32, 32), (64, 32, 32, 32)]
+
+
+# FP64 (x,t) planes and (y,z) tiles of two x-sites (an extent above 32 in
+# (z,t), Lx >= 16): t two-pass, z two-pass, both, a ragged last x-group
+# (odd Lx), both tile kinds with two-pass extents, the wider register tier
+# (162 = 9 x 18), a (y,z) tile beyond 80 KB (one 1024-thread block per
+# compute unit), 32 x 32 xy-planes (where the (x,t) planes replace the
+# two-tile (x,y) pass)
+TILE2_SHAPES = [(16, 4, 4, 48), (18, 3, 36, 4), (27, 4, 6, 36), (16, 6, 48, 96),
+                (48, 4, 4, 96), (36, 9, 54, 2), (16, 2, 2, 162), (16, 54, 54, 2),
+                (32, 32, 16, 64)]
+
+
+@pytest.mark.parametrize("L", TILE2_SHAPES)
+@pytest.mark.parametrize("sign", [-1, +1])
+def test_fft4d_tile2(lgf_gpu, L, sign):
+    test_fft4d(lgf_gpu, L, sign)
+
+
+@pytest.mark.parametrize("L", TILE2_SHAPES)
+def test_fourier_accelerate_tile2(lgf_gpu, L):
+    test_fourier_accelerate(lgf_gpu, L)
+
+
+@pytest.mark.parametrize("L", TILE2_SHAPES)
+def test_lockstep_sweeps_tile2(lgf_gpu, L):
+    test_lockstep_sweeps(lgf_gpu, L)
 
 
 @pytest.mark.parametrize("L", TWO_TILE_SHAPES)

@@ -285,6 +285,48 @@ __global__ void __launch_bounds__(NTHR)
     }
 }
 
+// Last pass of the FP32 sweeps of an SU(3) mixed solve in the (x,t)/(y,z)
+// split, fused with G(x) <- g(x) G(x): the (x,t) planes of all 4 fields of
+// one (y,z) slice per block (4 LDS regions), inverse t and x transforms, then
+// each site's 4 entries of L Delta form g and G goes from Gold into Gnew.
+// L Delta itself is not stored.
+// LDS of the 4-field planes of the fused inverse passes (one block per compute unit)
+constexpr size_t XY_ACC_LDS_MAX = 150 * 1024;
+// one block per compute unit: 16 waves at the lighter register tier, 8 at the other
+template <int RMAX> constexpr int tile2_acc_threads() { return RMAX <= 16 ? 1024 : 512; }
+template <int RMAX, bool EXACT>
+__global__ void __launch_bounds__(tile2_acc_threads<RMAX>())
+    k_fft_tile2_acc(geom g, const vec2_t<float> *__restrict__ D, const vec2_t<float> *__restrict__ tw,
+                    const vec2_t<float> *__restrict__ Gold, vec2_t<float> *__restrict__ Gnew,
+                    double c, tile2_plan tp, const dev_status *__restrict__ status) {
+    using T = float;
+    if (status->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    vec2_t<T> *lds = reinterpret_cast<vec2_t<T> *>(smem_raw);
+    const int Na = tp.Na, Nb = tp.Nb, PA = tp.PA, PB = tp.PB, REG = Nb * PB;
+    const long off = (long)xcd_block(blockIdx.x, gridDim.x) * tp.so;
+    const unsigned sb = (unsigned)tp.sb;  // the planes have one inner element (W = 1)
+    const int nel = Na * Nb;
+    for (int f = 0; f < 4; ++f)
+        for (int i = threadIdx.x; i < nel; i += tile2_acc_threads<RMAX>()) {
+            const int ja = i % Na, jb = i / Na;
+            lds[f * REG + ja * PA + jb * PB] = D[(long)f * g.S + off + (unsigned)ja + (unsigned)jb * sb];
+        }
+    __syncthreads();
+    auto colb = [Na, PA, REG](int cc) { return (cc / Na) * REG + (cc % Na) * PA; };  // cc = ja + Na f
+    auto cola = [Nb, PB, REG](int cc) { return (cc / Nb) * REG + (cc % Nb) * PB; };  // cc = jb + Nb f
+    lds_axis_fft<1, T, RMAX>(Nb, lds, 4 * Na, PB, colb, tw + tp.tb);
+    __syncthreads();
+    lds_axis_fft<1, T, RMAX>(Na, lds, 4 * Nb, PA, cola, tw + tp.ta);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nel; i += tile2_acc_threads<RMAX>()) {
+        const int ja = i % Na, jb = i / Na;
+        const vec2_t<T> *q = lds + ja * PA + jb * PB;
+        accumulate_G<EXACT>(ld<T>(q), ld<T>(q + REG), ld<T>(q + 2 * REG), ld<T>(q + 3 * REG), c,
+                            Gold, Gnew, g.S, off + (unsigned)ja + (unsigned)jb * sb);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Register-column transforms (register-axis extent up to 32).
 //
@@ -697,11 +739,12 @@ template <class T> void plan_two_tile(const geom &g, int ncu, fft_plan &p) {
         p.lds_zt2 = p.lds + (size_t)(g.Lx + g.Ly + g.Lz + g.Lt) * sizeof(T);
 }
 
-// (x,t) planes and (y,z) tiles of TILE2_W x-sites (FP64, an extent above 32
-// in (z,t)), where both tiles fit the budget and rows are at least 16 sites.
-constexpr int TILE2_W = 2;
+// (x,t) planes and (y,z) tiles of 32-byte rows (2 FP64 or 4 FP32 x-sites),
+// for an extent above 32 in (z,t), where both tiles fit and the planes' rows
+// are at least 16 sites.
 template <class T> void plan_tile2(const geom &g, size_t budget, fft_plan &p) {
-    if (!std::is_same<T, double>::value || p.rc) return;
+    if (p.rc) return;
+    constexpr int TILE2_W = 32 / (int)sizeof(vec2_t<T>);
     const size_t e = sizeof(vec2_t<T>);
     const long Lxy = (long)g.Lx * g.Ly, Lxyz = Lxy * g.Lz;
     const int ox = 0, oy = g.Lx, oz = g.Lx + g.Ly, ot = g.Lx + g.Ly + g.Lz;
@@ -855,6 +898,15 @@ template <class T> void fft_set_max_lds(const geom &g, const fft_plan &p) {
     set(reinterpret_cast<const void *>(&k_fft_tile2<T, M, 32, 256>), b);
         LGF_T2S(-1) LGF_T2S(0) LGF_T2S(1)
 #undef LGF_T2S
+        if constexpr (std::is_same<T, float>::value) {
+            const size_t a4 = 4 * p.t2a.lds;
+            if (a4 <= XY_ACC_LDS_MAX) {
+                set(reinterpret_cast<const void *>(&k_fft_tile2_acc<16, true>), a4);
+                set(reinterpret_cast<const void *>(&k_fft_tile2_acc<16, false>), a4);
+                set(reinterpret_cast<const void *>(&k_fft_tile2_acc<32, true>), a4);
+                set(reinterpret_cast<const void *>(&k_fft_tile2_acc<32, false>), a4);
+            }
+        }
     }
     if constexpr (std::is_same<T, double>::value) {
         if (p.xy2) {
@@ -948,14 +1000,15 @@ hipError_t launch_fft_xy(const geom &g, void *D, int dir, const void *tw, const 
     return hipGetLastError();
 }
 
-// The fused inverse (x,y) pass with G accumulation: register-column planes
-// holding all 4 fields in one block, or whole planes of all 4 fields in LDS.
-constexpr size_t XY_ACC_LDS_MAX = 150 * 1024;
+// The fused inverse pass with G accumulation: register-column planes
+// holding all 4 fields in one block, or whole (x,y) or (x,t) planes of all 4
+// fields in LDS.
 template <class T> inline size_t xy_acc_lds_bytes(const geom &g) {
     return (size_t)4 * g.Ly * (g.Lx + 1) * sizeof(vec2_t<T>);
 }
 template <class T> bool xy_acc_fusable(const geom &g, const fft_plan &pl) {
     if (g.nc != 3 || g.nf != 4) return false;
+    if (pl.t2) return std::is_same<T, float>::value && 4 * pl.t2a.lds <= XY_ACC_LDS_MAX;
     if (pl.xy == 0) return xy_fields_per_block<T>(g) == 4;
     if (pl.xy == 1) return xy_acc_lds_bytes<T>(g) <= XY_ACC_LDS_MAX;
     return false;
@@ -970,6 +1023,24 @@ hipError_t launch_fft_xy_inv_acc(const geom &g, void *D, const void *tw, const f
     auto twp = static_cast<const vec2_t<T> *>(tw);
     auto Go = static_cast<const vec2_t<T> *>(Gold);
     auto Gn = static_cast<vec2_t<T> *>(Gnew);
+    if constexpr (std::is_same<T, float>::value) {
+        if (pl.t2) {
+            const dim3 grid((unsigned)pl.t2a.nouter);
+            const size_t b = 4 * pl.t2a.lds;
+#define LGF_TA(R, E)                                                                          \
+    k_fft_tile2_acc<R, E><<<grid, tile2_acc_threads<R>(), b, st>>>(g, Dp, twp, Go, Gn, c, pl.t2a, \
+                                                                  status)
+            if (pl.t2a.rmax <= 16) {
+                if (exact) LGF_TA(16, true);
+                else LGF_TA(16, false);
+            } else {
+                if (exact) LGF_TA(32, true);
+                else LGF_TA(32, false);
+            }
+#undef LGF_TA
+            return hipGetLastError();
+        }
+    }
     if (pl.xy == 1) {
         const size_t b = xy_acc_lds_bytes<T>(g);
         const dim3 grid((unsigned)(g.Lz * g.Lt));

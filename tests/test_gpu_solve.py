@@ -130,12 +130,16 @@ def test_bad_arguments_raise(lgf_gpu):
 # planes with register spans up to 16 (48 wide) and 32 (Ly = 48 beside Lx = 32);
 # the update that shares links through LDS (xy-planes of a multiple of 256
 # sites, Lt a multiple of 4): x rows inside a block (32, 16 wide), rows that
-# straddle blocks (48 wide), two rows per block (128 wide), Lz = 3
+# straddle blocks (48 wide), two rows per block (128 wide), Lz = 3; the
+# (x,t)/(y,z) split with G accumulated in the last (x,t) pass (an extent above
+# 32 in (z,t)): the lighter and the wider register tier (Lx = 24), a ragged
+# last group of x-sites (27 = 6 x 4 + 3)
 @pytest.mark.parametrize("L,seed", [((8, 8, 8, 8), 35), ((32, 8, 4, 4), 36), ((48, 4, 4, 6), 37),
                                     ((32, 48, 2, 2), 38), ((27, 9, 4, 6), 39),
                                     ((256, 48, 2, 2), 40), ((16, 16, 3, 4), 41),
                                     ((48, 16, 2, 4), 42), ((128, 4, 2, 4), 43),
-                                    ((32, 32, 4, 8), 44)])
+                                    ((32, 32, 4, 8), 44), ((16, 4, 4, 48), 45),
+                                    ((24, 3, 36, 4), 46), ((27, 4, 6, 36), 47)])
 def test_mixed_iterate_applies_accumulated_transformation(lgf_gpu, L, seed):
     """FP32-phase lockstep: a mixed-precision context runs FP32 sweeps and
     applies the accumulated transformation to the FP64 input, so the result is
@@ -228,7 +232,7 @@ def test_exact_exp_lockstep(lgf_gpu, L, accelerate):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("L,seed", [((8, 8, 8, 8), inputs.CONFIG_SEEDS[("8^4", 0.5)]),
-                                    ((48, 4, 4, 6), 81)])
+                                    ((48, 4, 4, 6), 81), ((16, 4, 4, 48), 82)])
 def test_exact_exp_solve_matches_oracle(lgf_gpu, precision, L, seed):
     U, _ = inputs.make_config(L, 0.5, seed)
     ref = oracle.fix(U, ALPHA, 1e-14, 1000, exact_exp=True)

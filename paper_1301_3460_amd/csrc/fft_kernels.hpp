@@ -3,9 +3,13 @@
 //
 //   k_fft_xy_rc / k_fft_zt_rc  one axis held in registers, the other
 //                              exchanged through LDS (extents <= 32)
+//   k_fft_xy_rc2 / k_fft_zt_rc2  the same for FP64 32 x 32, two tiles per
+//                              block (the second loaded during the first)
 //   k_fft_xy                   a whole (x,y) plane in LDS (larger extents)
+//   k_fft_tile2 (_acc)         two axes per pass in LDS: (x,t) planes and
+//                              (y,z) tiles when (z,t) has an extent above 32
 //   k_fft_axis                 one axis per pass: W inner sites x the axis x B
-//                              slices in LDS (whatever the other two schemes
+//                              slices in LDS (whatever the other schemes
 //                              cannot hold)
 //
 // Twiddles: `tw` is the context's table buffer holding the axis tables of x,

@@ -38,11 +38,11 @@ BYTES_UPDATE_8 = 4 * 64 * 2 + 128  # update with 8-real links: R+W 4 x 64 B, R+W
 BYTES_UPDATE_SU2 = 4 * 32 * 2 + 32 * 2  # SU(2) update: R+W 4 links x 32 B, R+W 2 fields
 SD_TOL = 1e-10  # plain steepest descent needs thousands of sweeps at 32^4
 # algorithmic bytes per site of each sweep kernel: FP64, and the FP32 sweeps
-# of a mixed solve, whose inverse (x,y) pass also does G <- g G (R field 32,
+# of a mixed solve, whose last transform pass also does G <- g G (R field 32,
 # R+W G 96, the field itself not written back) and whose update forms the
-# links from the input copy U0 (R U0 192, R G 48, W field 32).  Where a plane
-# of all four fields does not fit one block (fp32_acc_fused), the accumulation
-# is a kernel of its own after a plain inverse pass (64 + 32 + 96).
+# links from the input copy U0 (R U0 192, R G 48, W field 32).  Where the
+# planes of all four fields do not fit one block (fp32_acc_fused), the
+# accumulation is a kernel of its own after a plain inverse pass (64 + 32 + 96).
 BYTES_PER_SITE = {
     "fp64": {"fft_xy_fwd": 128, "fft_zt": 128, "fft_xy_inv": 128, "update": 896, "finalize": 0},
     "fp32": {"fft_xy_fwd": 64, "fft_zt": 64, "fft_xy_inv": 128, "update": 272, "finalize": 0},
@@ -62,10 +62,16 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "update_32x4_fp64_traffic.json")
 
 
 def fp32_acc_fused(L) -> bool:
-    """Whether the FP32 sweeps accumulate G inside the inverse (x,y) pass: a
-    register-column plane (both extents up to 32) or a plane of all four FP32
-    fields within 150 KB of LDS (the library's rule)."""
-    Lx, Ly = L[0], L[1]
+    """Whether the FP32 sweeps accumulate G inside their last transform pass
+    (the library's rule).  With an extent above 32 in (z,t), Lx >= 16 and the
+    tiles within LDS, the last pass holds (x,t) planes and fuses when the four
+    fields' planes fit 150 KB; otherwise it holds (x,y) planes: a register-
+    column plane (both extents up to 32) or four planes within 150 KB."""
+    Lx, Ly, Lz, Lt = L
+    if Lz > 32 or Lt > 32:
+        xt = Lt * (Lx + 1) * 8
+        if Lx >= 16 and xt <= 80 * 1024 and Lz * (4 * Ly + 1) * 8 <= 160 * 1024 and Ly * Lz <= 65535:
+            return 4 * xt <= 150 * 1024
     if Lx <= 32 and Ly <= 32:
         return 4 * Lx <= 512
     return Ly * (Lx + 1) * 8 <= 160 * 1024 and 4 * Ly * (Lx + 1) * 8 <= 150 * 1024

@@ -26,16 +26,22 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 //     segment group, then t: three of four t-neighbour pairs are inside a
 //     block, and the blocks holding the y and z neighbours are at most
 //     g.sgroup positions apart in dispatch order on the same XCD, so their
-//     lines are still in that XCD's L2.
+//     lines are still in that XCD's L2.  When each XCD's range holds
+//     g.tslab > 1 slices of 4 t, the slices are walked inside z (after the
+//     segment group), so the t neighbours across two slices of one XCD are
+//     g.sgroup positions apart too instead of a whole slice.
 __device__ __forceinline__ long block_site(const geom &g, int b, int nb, int tid) {
     const int B = xcd_block(b, nb);
     if (!g.tblock) return (long)B * SITE_BLOCK + tid;
     const int Lxy = g.Lx * g.Ly, G = g.sgroup, ngrp = (Lxy >> 6) / G;
     const int sg = B % G;
     int r = B / G;
+    const int sl = r % g.tslab;
+    r /= g.tslab;
     const int z = r % g.Lz;
     r /= g.Lz;
-    const int seg = (r % ngrp) * G + sg, t = (r / ngrp) * 4 + (tid >> 6);
+    const int slab = (r / ngrp) * g.tslab + sl;
+    const int seg = (r % ngrp) * G + sg, t = slab * 4 + (tid >> 6);
     return (long)seg * 64 + (tid & 63) + (long)Lxy * (z + (long)g.Lz * t);
 }
 

@@ -53,6 +53,8 @@ struct geom {
     // site-kernel tiling (see block_site): 0 consecutive sites; 1 64 xy-sites
     // x 4 t (needs Lx*Ly % 64 == 0, Lt % 4 == 0), in groups of sgroup segments
     int tblock = 0, sgroup = 1;
+    // slices of 4 t in each XCD's range of blocks, walked inside z when > 1
+    int tslab = 1;
     // working link format, reals per link: 12 (rows 0,1; row 2 rebuilt), 18
     // (all three rows) or 8 (the minimal form of su3.hpp)
     int lf = 12;
@@ -85,6 +87,9 @@ inline geom make_geom(const int L[4], int nc) {
     g.tblock = ((long)L[0] * L[1] % 64 == 0 && L[3] % 4 == 0) ? 1 : 0;
     const long nseg = (long)L[0] * L[1] / 64;
     g.sgroup = (nseg % 4 == 0) ? 4 : (nseg % 2 == 0) ? 2 : 1;
+    // the 8 XCD ranges split the slices of 4 t evenly
+    const int nslab = L[3] / 4;
+    g.tslab = (g.tblock && nslab % 8 == 0 && nslab > 8) ? nslab / 8 : 1;
     return g;
 }
 

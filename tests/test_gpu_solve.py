@@ -133,13 +133,15 @@ def test_bad_arguments_raise(lgf_gpu):
 # straddle blocks (48 wide), two rows per block (128 wide), Lz = 3; the
 # (x,t)/(y,z) split with G accumulated in the last (x,t) pass (an extent above
 # 32 in (z,t)): the lighter and the wider register tier (Lx = 24), a ragged
-# last group of x-sites (27 = 6 x 4 + 3)
+# last group of x-sites (27 = 6 x 4 + 3); two t groups per XCD range of
+# blocks (16 slices of 4 t)
 @pytest.mark.parametrize("L,seed", [((8, 8, 8, 8), 35), ((32, 8, 4, 4), 36), ((48, 4, 4, 6), 37),
                                     ((32, 48, 2, 2), 38), ((27, 9, 4, 6), 39),
                                     ((256, 48, 2, 2), 40), ((16, 16, 3, 4), 41),
                                     ((48, 16, 2, 4), 42), ((128, 4, 2, 4), 43),
                                     ((32, 32, 4, 8), 44), ((16, 4, 4, 48), 45),
-                                    ((24, 3, 36, 4), 46), ((27, 4, 6, 36), 47)])
+                                    ((24, 3, 36, 4), 46), ((27, 4, 6, 36), 47),
+                                    ((16, 16, 2, 64), 48)])
 def test_mixed_iterate_applies_accumulated_transformation(lgf_gpu, L, seed):
     """FP32-phase lockstep: a mixed-precision context runs FP32 sweeps and
     applies the accumulated transformation to the FP64 input, so the result is

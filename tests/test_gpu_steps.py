@@ -34,6 +34,8 @@ SHAPES = [
     (256, 2, 2, 2), (2, 2, 4, 256), (27, 27, 3, 2),
     # (x,y) planes beyond one LDS tile: a separate x pass and y pass
     (256, 48, 2, 2), (243, 81, 2, 2),
+    # several slices of 4 t per XCD range of site blocks (walked inside z)
+    (8, 8, 4, 64), (16, 4, 2, 96),
 ]
 
 

@@ -407,12 +407,16 @@ def test_mixed_fp32_phase_hands_over_when_it_stalls(lgf_gpu):
 
 # ----------------------------------------------- FP32 Fourier field in FP64 sweeps
 
+# register-column transforms (8^4) and the (x,t)/(y,z) split (an extent above
+# 32 in (z,t)) of the FP32 field
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_field32_solve_matches_oracle(lgf_gpu, precision):
+@pytest.mark.parametrize("L,seed", [((8, 8, 8, 8), inputs.CONFIG_SEEDS[("8^4", 0.5)]),
+                                    ((16, 4, 4, 48), 83)])
+def test_field32_solve_matches_oracle(lgf_gpu, precision, L, seed):
     """The Fourier field in FP32 changes only the step direction (by ~1e-7,
     relative); the fixed point, the stopping test and the sweep count are
     those of the FP64 method."""
-    U, _ = inputs.make_config((8, 8, 8, 8), 0.5, inputs.CONFIG_SEEDS[("8^4", 0.5)])
+    U, _ = inputs.make_config(L, 0.5, seed)
     ref = oracle.fix(U, ALPHA, 1e-14, 1000)
     Ug = gpu(U)
     r = lgf_gpu.fix(Ug, ALPHA, 1e-14, precision=precision, max_iter=1000, field_bits=32)

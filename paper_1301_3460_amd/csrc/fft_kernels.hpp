@@ -223,8 +223,9 @@ __global__ void __launch_bounds__(AXIS_BLOCK) __attribute__((amdgpu_waves_per_eu
 // forward, b forward / scaling / b inverse, a inverse.
 // ---------------------------------------------------------------------------
 
-// block size of the two-axis tiles: two blocks of this size share a compute
-// unit (the LDS tile), so the lighter register tier takes twice the threads
+// NTHR: threads per block; at the lighter register tier 512 where two tiles
+// share a compute unit and 1024 where one tile fills it (16 waves either
+// way), 256 at the wider tier
 template <class T, int MODE, int RMAX, int NTHR>
 __global__ void __launch_bounds__(NTHR)
     k_fft_tile2(geom g, vec2_t<T> *__restrict__ D, const vec2_t<T> *__restrict__ tw,

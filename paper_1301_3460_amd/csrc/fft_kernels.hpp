@@ -57,6 +57,54 @@ __device__ __forceinline__ T fa_factor(T base, T pz, T p2max_over_V) {
     return (base < T(0) || p2 == T(0)) ? T(0) : p2max_over_V * recip(p2);
 }
 
+// Element i = a + A (b + B c) of a tile as its digits (a, b, c), advanced by
+// a fixed step with one carry per digit (the step's a and b digits are below
+// A and B, so each sum stays below twice the radix).
+struct tile_idx {
+    int a, b, c;
+    __device__ __forceinline__ tile_idx(int i, int A, int B) {
+        a = i % A;
+        const int r = i / A;
+        b = r % B;
+        c = r / B;
+    }
+    __device__ __forceinline__ void step(const tile_idx &d, int A, int B) {
+        a += d.a;
+        int k = a >= A;
+        if (k) a -= A;
+        b += d.b + k;
+        k = b >= B;
+        if (k) b -= B;
+        c += d.c + k;
+    }
+};
+
+// Copies the nel elements of a tile (digits a, b, c with radices A, B) from
+// one memory to the other: each thread issues up to CH loads (get) before its
+// first store (put), so that their latencies overlap (CH = 1: one round trip
+// per element).
+template <int NTHR, int CH, class V, class Get, class Put>
+__device__ __forceinline__ void tile_copy(int nel, int A, int B, Get get, Put put) {
+    const tile_idx d(NTHR, A, B);
+    tile_idx q((int)threadIdx.x, A, B);
+    for (int i0 = threadIdx.x; i0 < nel; i0 += CH * NTHR) {
+        V v[CH];
+        tile_idx p = q;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            if (i0 + k * NTHR < nel) v[k] = get(p);
+            p.step(d, A, B);
+        }
+        p = q;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            if (i0 + k * NTHR < nel) put(p, v[k]);
+            p.step(d, A, B);
+        }
+        q = p;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // (x, y) plane transform: one plane of one field per block, LDS [y][x+1]
 // ---------------------------------------------------------------------------
@@ -244,14 +292,29 @@ __global__ void __launch_bounds__(NTHR)
     // offsets inside one field are below 2^31 (the volume is)
     const unsigned sa = (unsigned)tp.sa, sb = (unsigned)tp.sb;
     const int nel = W * Na * Nb;
-    for (int i = threadIdx.x; i < nel; i += NTHR) {
-        const int w = i % W, r = i / W, ja = r % Na, jb = r / Na;
-        vec2_t<T> v;
-        v.x = 0;
-        v.y = 0;
-        if (w < Wt) v = F[(unsigned)ja * sa + (unsigned)jb * sb + (unsigned)w];
-        lds[w + ja * PA + jb * PB] = v;
-    }
+    // Loads per thread in flight in the copies, as measured at 48^3 x 96:
+    // nine (0.33 against 0.41 ms in the FP64 first pass), three in the FP32
+    // first pass (0.17 against 0.20), one in the FP64 middle pass, whose
+    // 32-byte rows are shared by four blocks (0.68 ms; 0.73 with nine, 0.92
+    // with three).  Stores are batched in the first pass only (the FP64 last
+    // pass: 0.34 ms with single stores, 0.37 batched).
+    constexpr int CHL = (MODE == 0 && sizeof(T) == 8) ? 1 : (MODE < 0 && sizeof(T) == 4) ? 3 : 9;
+    constexpr int CHS = MODE < 0 ? CHL : 1;
+    // tile digits (w, ja, jb); a padding column of a ragged group reads its
+    // group's last column and stores zero
+    auto hbm = [=](const tile_idx &p) { return F + ((unsigned)p.b * sa + (unsigned)p.c * sb + (unsigned)p.a); };
+    auto sh = [=](const tile_idx &p) { return lds + (p.a + p.b * PA + p.c * PB); };
+    tile_copy<NTHR, CHL, vec2_t<T>>(
+        nel, W, Na,
+        [=](const tile_idx &p) {
+            tile_idx q = p;
+            q.a = min(q.a, Wt - 1);
+            return *hbm(q);
+        },
+        [=](const tile_idx &p, vec2_t<T> v) {
+            if (p.a >= Wt) v.x = v.y = T(0);
+            *sh(p) = v;
+        });
     __syncthreads();
     const vec2_t<T> *twa = tw + tp.ta, *twb = tw + tp.tb;
     auto cola = [W, PB](int c) { return (c % W) + (c / W) * PB; };  // c = w + W*jb
@@ -284,10 +347,11 @@ __global__ void __launch_bounds__(NTHR)
         lds_axis_fft<1, T, RMAX>(Na, lds, W * Nb, PA, cola, twa);
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < nel; i += NTHR) {
-        const int w = i % W, r = i / W, ja = r % Na, jb = r / Na;
-        if (w < Wt) F[(unsigned)ja * sa + (unsigned)jb * sb + (unsigned)w] = lds[w + ja * PA + jb * PB];
-    }
+    tile_copy<NTHR, CHS, vec2_t<T>>(
+        nel, W, Na, [=](const tile_idx &p) { return *sh(p); },
+        [=](const tile_idx &p, vec2_t<T> v) {
+            if (p.a < Wt) *hbm(p) = v;
+        });
 }
 
 // Last pass of the FP32 sweeps of an SU(3) mixed solve in the (x,t)/(y,z)
@@ -312,11 +376,12 @@ __global__ void __launch_bounds__(tile2_acc_threads<RMAX>())
     const long off = (long)xcd_block(blockIdx.x, gridDim.x) * tp.so;
     const unsigned sb = (unsigned)tp.sb;  // the planes have one inner element (W = 1)
     const int nel = Na * Nb;
-    for (int f = 0; f < 4; ++f)
-        for (int i = threadIdx.x; i < nel; i += tile2_acc_threads<RMAX>()) {
-            const int ja = i % Na, jb = i / Na;
-            lds[f * REG + ja * PA + jb * PB] = D[(long)f * g.S + off + (unsigned)ja + (unsigned)jb * sb];
-        }
+    // digits (ja, jb, field); nine loads per thread in flight (0.33 ms
+    // against 0.38 at 48^3 x 96)
+    tile_copy<tile2_acc_threads<RMAX>(), 9, vec2_t<T>>(
+        4 * nel, Na, Nb,
+        [=](const tile_idx &p) { return D[(long)p.c * g.S + off + (unsigned)p.a + (unsigned)p.b * sb]; },
+        [=](const tile_idx &p, vec2_t<T> v) { lds[p.c * REG + p.a * PA + p.b * PB] = v; });
     __syncthreads();
     auto colb = [Na, PA, REG](int cc) { return (cc / Na) * REG + (cc % Na) * PA; };  // cc = ja + Na f
     auto cola = [Nb, PB, REG](int cc) { return (cc / Nb) * REG + (cc % Nb) * PB; };  // cc = jb + Nb f

@@ -370,7 +370,11 @@ __global__ void __launch_bounds__(SITE_BLOCK)
 // per-link projections change the rounding order of the sums, not the
 // quantities.  Partial sums go out per group of SITE_BLOCK threads, so the
 // finalize reads the same number of partials as after k_update.
-constexpr int UPDS_XY = 256, UPDS_T = 4, UPDS_THREADS = UPDS_XY * UPDS_T;
+// Blocks of 128 xy-sites x 4 t (512 threads, 64 KB of LDS) let two blocks
+// share a compute unit, so that one block's loads overlap the other's
+// arithmetic: 73 against 82 us at 32^4 and 797 against 828 us at 48^3 x 96
+// for one block of 256 x 4 (or 256 x 2: 74 / 848 us; 128 x 2: 73 / 855 us).
+constexpr int UPDS_XY = 128, UPDS_T = 4, UPDS_THREADS = UPDS_XY * UPDS_T;
 constexpr size_t UPDS_LDS = (size_t)8 * 4 * UPDS_THREADS * sizeof(float);
 
 inline bool update_shared_ok(const geom &g) {
@@ -429,7 +433,8 @@ __device__ __forceinline__ void group_sum2(double a, double b, double *partials,
     }
 }
 
-__global__ void __launch_bounds__(UPDS_THREADS)
+// four waves per SIMD: two blocks per compute unit (at most 128 VGPRs)
+__global__ void __launch_bounds__(UPDS_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
     k_update_shared32(geom g, const float2 *__restrict__ Lin, const float2 *__restrict__ GX,
                       float2 *__restrict__ Dout, double *__restrict__ partials,
                       const dev_status *__restrict__ status) {

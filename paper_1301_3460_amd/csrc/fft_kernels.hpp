@@ -317,9 +317,10 @@ __global__ void __launch_bounds__(NTHR)
     // Loads per thread in flight in the copies, as measured at 48^3 x 96:
     // nine (0.33 against 0.41 ms in the FP64 first pass), three in the FP32
     // first pass (0.17 against 0.20), one in the FP64 middle pass, whose
-    // 32-byte rows are shared by four blocks (0.68 ms; 0.73 with nine, 0.92
-    // with three).  Stores are batched in the first pass only (the FP64 last
-    // pass: 0.34 ms with single stores, 0.37 batched).
+    // 32-byte rows are shared by four blocks (0.68 ms; 0.94 with nine loads,
+    // 0.73 with nine loads and nine stores, 0.92 with three of each).  Stores
+    // are batched in the first pass only (the FP64 last pass: 0.34 ms with
+    // single stores, 0.37 batched).
     constexpr int CHL = (MODE == 0 && sizeof(T) == 8) ? 1 : (MODE < 0 && sizeof(T) == 4) ? 3 : 9;
     constexpr int CHS = MODE < 0 ? CHL : 1;
     // tile digits (w, ja, jb); a padding column of a ragged group reads its
